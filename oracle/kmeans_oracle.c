@@ -1,0 +1,452 @@
+/*
+ * kmeans_oracle.c -- plain, slow, CPU reference for mixed-precision Lloyd
+ * k-means (Carson, Chen, Liu, "Computing k-means in Mixed Precision").
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product path may link, load or
+ * call this file; only the test suite, the smoke check and the CPU-baseline
+ * leg of the benchmark do.  It shares no code, header, table or constant with
+ * the GPU library.
+ *
+ * What it computes, and where each definition comes from:
+ *
+ *   O1  assign   -- squared distance by the direct formula eq:dist-direct,
+ *                   d(x,y)^2 = (x-y)^T (x-y), accumulated in FP64 over the
+ *                   coordinates in index order, from the FP32 inputs
+ *                   converted exactly to FP64; label = smallest index among
+ *                   the minimisers (tie rule: the paper is silent); the SSE
+ *                   of eq:sse as a pairwise FP64 sum over the points.
+ *                   Error <= gamma_{d+2}(u_64) d^2 (Theorem thm:dist-diff).
+ *   O2  update   -- centre update of eq:center: per-cluster coordinate sums
+ *                   in FP64 in ascending point order, one division, one
+ *                   rounding to FP32 (centres are stored in working precision,
+ *                   Algorithm alg:mp-kmeans).  An empty cluster keeps its
+ *                   previous centre (the paper reinitialises empty clusters
+ *                   without saying how).
+ *   O3  lloyd    -- Algorithm alg:kmeans / alg:mp-kmeans without the
+ *                   normalisation step: t_max rounds of assign + update,
+ *                   break when max_j ||c_j^t - c_j^{t-1}|| < tau, then one
+ *                   final assignment.
+ *   O4  mp rows  -- emulation of the quantities that decide the mixed-precision
+ *                   reliability test of eq:fallback-rule-mp / Algorithm
+ *                   alg:mp-dist: round-to-nearest-even quantisation to FP16 or
+ *                   BF16 written from the IEEE 754 definition, the squared
+ *                   distance q of the quantised vectors, S = ||x~||^2+||c~||^2,
+ *                   the margin q - alpha*S, and a per-pair classification
+ *                   (surely corrected / surely kept / ambiguous) together with
+ *                   an a-posteriori error bound on the value a GPU evaluation
+ *                   in FP32 arithmetic may return (Theorem thm:dist-exp applied
+ *                   to the quantised inputs, conversion bound C(x,y) of
+ *                   Section 4.3).
+ *
+ * Build: gcc -O2 -ffp-contract=off -fopenmp -shared -fPIC (no fast-math).
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+/* ---------------------------------------------------------------------- */
+/* Floating-point formats (Table table:float-arith-parameter)             */
+/* ---------------------------------------------------------------------- */
+/* fmt: 0 = binary16, 1 = bfloat16, 2 = binary32, 3 = binary64.
+ * t = significand bits including the implicit bit; emin = exponent of the
+ * smallest normal number; emax = exponent of the largest finite number. */
+static const int FMT_T[4] = {11, 8, 24, 53};
+static const int FMT_EMIN[4] = {-14, -126, -126, -1022};
+static const int FMT_EMAX[4] = {15, 127, 127, 1023};
+
+int oracle_fmt_params(int fmt, int *t, int *emin, int *emax) {
+  if (fmt < 0 || fmt > 3) return -1;
+  *t = FMT_T[fmt];
+  *emin = FMT_EMIN[fmt];
+  *emax = FMT_EMAX[fmt];
+  return 0;
+}
+
+/* unit roundoff u = 2^-t for round to nearest */
+double oracle_unit_roundoff(int fmt) {
+  if (fmt < 0 || fmt > 3) return NAN;
+  return ldexp(1.0, -FMT_T[fmt]);
+}
+
+/* largest finite number (2 - 2^(1-t)) * 2^emax */
+double oracle_fmt_max(int fmt) {
+  if (fmt < 0 || fmt > 3) return NAN;
+  return ldexp(2.0 - ldexp(1.0, 1 - FMT_T[fmt]), FMT_EMAX[fmt]);
+}
+
+/* smallest positive normal number 2^emin */
+double oracle_fmt_min_normal(int fmt) {
+  if (fmt < 0 || fmt > 3) return NAN;
+  return ldexp(1.0, FMT_EMIN[fmt]);
+}
+
+/* gamma_m = m u / (1 - m u), defined for m u < 1 (Section 4, after
+ * eq:fpmode-vecprod); +inf otherwise. */
+double oracle_gamma(double m, double u) {
+  double mu = m * u;
+  if (!(mu < 1.0)) return INFINITY;
+  return mu / (1.0 - mu);
+}
+
+/* Round a binary32 value to the nearest value of format fmt (0: binary16,
+ * 1: bfloat16), ties to even, with gradual underflow and overflow to
+ * infinity, as IEEE 754 round-to-nearest-even defines it.  The result is
+ * returned as a double (every such value is exactly representable).
+ *
+ * Method: for |x| in [2^e, 2^(e+1)) with e >= emin the spacing of the target
+ * format is 2^(e+1-t); below 2^emin the spacing is the subnormal quantum
+ * 2^(emin+1-t).  x / spacing is rounded to the nearest integer, ties to even
+ * (exact in double, default rounding mode), and scaled back.  A result whose
+ * magnitude exceeds the largest finite number overflows to infinity; that
+ * happens exactly when |x| >= (2 - 2^-t) * 2^emax. */
+double oracle_round_low(float xf, int fmt) {
+  double x = (double)xf;
+  if (fmt != 0 && fmt != 1) return NAN;
+  if (isnan(x)) return x;
+  if (isinf(x)) return x;
+  if (x == 0.0) return x; /* keeps the sign of zero */
+  int t = FMT_T[fmt], emin = FMT_EMIN[fmt];
+  double ax = fabs(x);
+  int e;
+  frexp(ax, &e); /* ax = f * 2^e, f in [0.5, 1): ax in [2^(e-1), 2^e) */
+  int expo = e - 1;
+  if (expo < emin) expo = emin;
+  double spacing = ldexp(1.0, expo + 1 - t);
+  double r = nearbyint(ax / spacing) * spacing;
+  if (r > oracle_fmt_max(fmt)) r = INFINITY;
+  return x < 0 ? -r : r;
+}
+
+void oracle_quantize(const float *in, int64_t count, int fmt, double *out) {
+  for (int64_t i = 0; i < count; ++i) out[i] = oracle_round_low(in[i], fmt);
+}
+
+/* ---------------------------------------------------------------------- */
+/* O1: direct-formula distances, argmin, SSE                               */
+/* ---------------------------------------------------------------------- */
+
+/* eq:dist-direct in FP64, coordinates in index order. */
+double oracle_sqdist(const float *x, const float *y, int d) {
+  double s = 0.0;
+  for (int l = 0; l < d; ++l) {
+    double diff = (double)x[l] - (double)y[l];
+    s += diff * diff;
+  }
+  return s;
+}
+
+/* Pairwise (cascade) summation of v[0..n) in FP64. */
+static double pairwise_sum(const double *v, int64_t n) {
+  if (n <= 8) {
+    double s = 0.0;
+    for (int64_t i = 0; i < n; ++i) s += v[i];
+    return s;
+  }
+  int64_t h = n / 2;
+  return pairwise_sum(v, h) + pairwise_sum(v + h, n - h);
+}
+
+double oracle_pairwise_sum(const double *v, int64_t n) { return pairwise_sum(v, n); }
+
+/* D[i*k + j] = d(x_i, c_j)^2 for the m rows of X. */
+void oracle_dist_rows(const float *X, int64_t m, int d, const float *C, int k,
+                      double *D) {
+#pragma omp parallel for schedule(static)
+  for (int64_t i = 0; i < m; ++i)
+    for (int j = 0; j < k; ++j)
+      D[i * (int64_t)k + j] = oracle_sqdist(X + i * (int64_t)d, C + (int64_t)j * d, d);
+}
+
+/* For each point: label = smallest index attaining min_j d_ij, mind = that
+ * distance (FP64).  sse (nullable) receives the pairwise sum of mind. */
+void oracle_assign(const float *X, int64_t n, int d, const float *C, int k,
+                   int32_t *labels, double *mind, double *sse) {
+  double *md = mind;
+  if (md == NULL) md = (double *)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
+#pragma omp parallel for schedule(static)
+  for (int64_t i = 0; i < n; ++i) {
+    const float *x = X + i * (int64_t)d;
+    int best = 0;
+    double bd = oracle_sqdist(x, C, d);
+    for (int j = 1; j < k; ++j) {
+      double v = oracle_sqdist(x, C + (int64_t)j * d, d);
+      if (v < bd) { /* strict: the first minimiser is kept */
+        bd = v;
+        best = j;
+      }
+    }
+    labels[i] = best;
+    md[i] = bd;
+  }
+  if (sse) *sse = pairwise_sum(md, n);
+  if (mind == NULL) free(md);
+}
+
+/* ---------------------------------------------------------------------- */
+/* O2: centre update                                                       */
+/* ---------------------------------------------------------------------- */
+
+/* C_new[j] = fl32( (sum_{i: label_i = j} x_i) / m_j ), sums in FP64 in
+ * ascending i; m_j = 0 keeps C_old[j].  counts (nullable) receives m_j.
+ * shift (nullable) receives max_j ||C_new[j] - C_old[j]|| (FP64).
+ * Returns the number of empty clusters, or -1 on a label out of range. */
+int64_t oracle_update(const float *X, int64_t n, int d, const int32_t *labels,
+                      int k, const float *C_old, float *C_new, int64_t *counts,
+                      double *shift) {
+  double *s = (double *)calloc((size_t)k * (size_t)d, sizeof(double));
+  int64_t *m = (int64_t *)calloc((size_t)k, sizeof(int64_t));
+  if (!s || !m) {
+    free(s);
+    free(m);
+    return -2;
+  }
+  for (int64_t i = 0; i < n; ++i) {
+    int j = labels[i];
+    if (j < 0 || j >= k) {
+      free(s);
+      free(m);
+      return -1;
+    }
+    const float *x = X + i * (int64_t)d;
+    double *sj = s + (int64_t)j * d;
+    for (int l = 0; l < d; ++l) sj[l] += (double)x[l];
+    m[j] += 1;
+  }
+  int64_t empty = 0;
+  double maxshift = 0.0;
+  for (int j = 0; j < k; ++j) {
+    double mv2 = 0.0;
+    for (int l = 0; l < d; ++l) {
+      float nv;
+      if (m[j] > 0)
+        nv = (float)(s[(int64_t)j * d + l] / (double)m[j]);
+      else
+        nv = C_old[(int64_t)j * d + l];
+      double diff = (double)nv - (double)C_old[(int64_t)j * d + l];
+      mv2 += diff * diff;
+      C_new[(int64_t)j * d + l] = nv;
+    }
+    if (m[j] == 0) empty += 1;
+    double mv = sqrt(mv2);
+    if (mv > maxshift) maxshift = mv;
+    if (counts) counts[j] = m[j];
+  }
+  if (shift) *shift = maxshift;
+  free(s);
+  free(m);
+  return empty;
+}
+
+/* ---------------------------------------------------------------------- */
+/* O3: Lloyd's algorithm                                                   */
+/* ---------------------------------------------------------------------- */
+
+/* C (k x d) holds the initial centres on entry and the final ones on exit.
+ * sse_hist (nullable, max_iter+1 entries): SSE of each assignment, the last
+ * filled entry being the final assignment.  shift_hist (nullable, max_iter).
+ * labels/mind receive the final assignment.  Returns the number of update
+ * rounds performed (<= max_iter), or a negative value on error. */
+int oracle_lloyd(const float *X, int64_t n, int d, int k, float *C, int max_iter,
+                 double tol, int32_t *labels, double *mind, double *sse_hist,
+                 double *shift_hist) {
+  float *Cn = (float *)malloc(sizeof(float) * (size_t)k * (size_t)d);
+  if (!Cn) return -2;
+  int t;
+  for (t = 0; t < max_iter; ++t) {
+    double sse = 0.0, shift = 0.0;
+    oracle_assign(X, n, d, C, k, labels, mind, &sse);
+    if (sse_hist) sse_hist[t] = sse;
+    if (oracle_update(X, n, d, labels, k, C, Cn, NULL, &shift) < 0) {
+      free(Cn);
+      return -1;
+    }
+    memcpy(C, Cn, sizeof(float) * (size_t)k * (size_t)d);
+    if (shift_hist) shift_hist[t] = shift;
+    if (shift < tol) { /* strict, as in the stopping test of alg:kmeans */
+      t += 1;
+      break;
+    }
+  }
+  double sse = 0.0;
+  oracle_assign(X, n, d, C, k, labels, mind, &sse);
+  if (sse_hist) sse_hist[t] = sse;
+  free(Cn);
+  return t;
+}
+
+/* ---------------------------------------------------------------------- */
+/* O4: mixed-precision reliability test, emulated                           */
+/* ---------------------------------------------------------------------- */
+
+/*
+ * For the m rows of X against all k centres, with x~ = RNE_fmt(x), c~ = RNE_fmt(c)
+ * (fmt 0 = FP16, 1 = BF16):
+ *
+ *   dist[i,j] = d(x_i, c_j)^2 from the original data (O1)
+ *   q[i,j]    = d(x~_i, c~_j)^2 in FP64 (the quantised distance)
+ *   S[i,j]    = ||x~_i||^2 + ||c~_j||^2
+ *   P[i,j]    = |x~_i|^T |c~_j|
+ *
+ * The reliability test of eq:quantis-reliability-test keeps the low-precision
+ * value iff  d^ > alpha * S  (alpha = rho~ * 2 gamma^l_{d+2} in the equation
+ * form, rho~ gamma^l_{d+2} in the listing form -- the caller passes the value
+ * the GPU uses).  A GPU evaluates d^ with inputs x~, c~ in FP32 arithmetic, so
+ * by Theorem thm:dist-exp (with the FP32 unit roundoff doubled to cover any
+ * rounding mode of the accumulator)
+ *
+ *   |d^ - q| <= A := gamma'_{d+4} (S + 2P),   gamma' = gamma(., 2 u_32),
+ *
+ * and the FP32 evaluation of alpha*S is off by at most alpha*A.  Hence
+ *
+ *   cls = -1 (surely corrected) if q - alpha S < -band,
+ *   cls = +1 (surely kept)      if q - alpha S > +band,
+ *   cls =  0 (ambiguous)        otherwise,          band := (1 + alpha) A.
+ *
+ * B[i,j] bounds |D - dist| for the value D the GPU reports for the pair:
+ *   kept:      |q - dist| + A + gamma_{d+2}(u_64) dist
+ *   corrected: 2 u_32 dist   (FP64 direct formula rounded once to FP32,
+ *                             eq:fallback-rule-mp and alg:mp-dist)
+ *   ambiguous: the larger of the two.
+ * alpha < 0 means "never correct" (uniform low precision, no fallback).
+ *
+ * Every output pointer except dist is nullable.  Returns the number of pairs
+ * whose inputs overflow the low format (those get cls = -2, B = inf).
+ */
+int64_t oracle_mp_rows(const float *X, int64_t m, int d, const float *C, int k,
+                       int fmt, double alpha, double *dist, double *q_out,
+                       double *S_out, double *A_out, double *B_out,
+                       int8_t *cls_out) {
+  double u32 = oracle_unit_roundoff(2), u64 = oracle_unit_roundoff(3);
+  double gp = oracle_gamma((double)(d + 4), 2.0 * u32);
+  double g64 = oracle_gamma((double)(d + 2), u64);
+  double *Ct = (double *)malloc(sizeof(double) * (size_t)k * (size_t)d);
+  double *nc = (double *)malloc(sizeof(double) * (size_t)k);
+  int *cbad = (int *)calloc((size_t)k, sizeof(int));
+  if (!Ct || !nc || !cbad) {
+    free(Ct);
+    free(nc);
+    free(cbad);
+    return -1;
+  }
+  for (int j = 0; j < k; ++j) {
+    double s = 0.0;
+    for (int l = 0; l < d; ++l) {
+      double v = oracle_round_low(C[(int64_t)j * d + l], fmt);
+      if (isinf(v) || isnan(v)) cbad[j] = 1;
+      Ct[(int64_t)j * d + l] = v;
+      s += v * v;
+    }
+    nc[j] = s;
+  }
+  int64_t nbad = 0;
+#pragma omp parallel for schedule(static) reduction(+ : nbad)
+  for (int64_t i = 0; i < m; ++i) {
+    const float *x = X + i * (int64_t)d;
+    double *xt = (double *)malloc(sizeof(double) * (size_t)d);
+    double nx = 0.0;
+    int xbad = 0;
+    for (int l = 0; l < d; ++l) {
+      xt[l] = oracle_round_low(x[l], fmt);
+      if (isinf(xt[l]) || isnan(xt[l])) xbad = 1;
+      nx += xt[l] * xt[l];
+    }
+    for (int j = 0; j < k; ++j) {
+      int64_t o = i * (int64_t)k + j;
+      const double *ct = Ct + (int64_t)j * d;
+      double dd = oracle_sqdist(x, C + (int64_t)j * d, d);
+      double q = 0.0, P = 0.0;
+      for (int l = 0; l < d; ++l) {
+        double diff = xt[l] - ct[l];
+        q += diff * diff;
+        P += fabs(xt[l]) * fabs(ct[l]);
+      }
+      double S = nx + nc[j];
+      double A = gp * (S + 2.0 * P);
+      int8_t cls;
+      double B;
+      double Bk = fabs(q - dd) + A + g64 * dd;
+      double Bc = 2.0 * u32 * dd;
+      if (xbad || cbad[j]) {
+        cls = -2;
+        B = INFINITY;
+        nbad += 1;
+      } else if (alpha < 0.0) {
+        cls = 1;
+        B = Bk;
+      } else {
+        double margin = q - alpha * S;
+        double band = (1.0 + alpha) * A;
+        if (margin < -band) {
+          cls = -1;
+          B = Bc;
+        } else if (margin > band) {
+          cls = 1;
+          B = Bk;
+        } else {
+          cls = 0;
+          B = Bk > Bc ? Bk : Bc;
+        }
+      }
+      dist[o] = dd;
+      if (q_out) q_out[o] = q;
+      if (S_out) S_out[o] = S;
+      if (A_out) A_out[o] = A;
+      if (B_out) B_out[o] = B;
+      if (cls_out) cls_out[o] = cls;
+    }
+    free(xt);
+  }
+  free(Ct);
+  free(nc);
+  free(cbad);
+  return nbad;
+}
+
+/* Counts of the O4 classes over all pairs, without materialising them:
+ * counts[0] = surely corrected, counts[1] = ambiguous, counts[2] = surely kept,
+ * counts[3] = pairs whose inputs overflow the low format. */
+void oracle_mp_count(const float *X, int64_t m, int d, const float *C, int k,
+                     int fmt, double alpha, int64_t *counts) {
+  const int64_t rows = 64;
+  int64_t c0 = 0, c1 = 0, c2 = 0, c3 = 0;
+  double *dist = (double *)malloc(sizeof(double) * (size_t)rows * (size_t)k);
+  int8_t *cls = (int8_t *)malloc((size_t)rows * (size_t)k);
+  for (int64_t s = 0; s < m; s += rows) {
+    int64_t e = s + rows < m ? s + rows : m;
+    oracle_mp_rows(X + s * (int64_t)d, e - s, d, C, k, fmt, alpha, dist, NULL,
+                   NULL, NULL, NULL, cls);
+    for (int64_t o = 0; o < (e - s) * (int64_t)k; ++o) {
+      if (cls[o] == -1) c0++;
+      else if (cls[o] == 0) c1++;
+      else if (cls[o] == 1) c2++;
+      else c3++;
+    }
+  }
+  free(dist);
+  free(cls);
+  counts[0] = c0;
+  counts[1] = c1;
+  counts[2] = c2;
+  counts[3] = c3;
+}
+
+/* Number of threads the OpenMP runtime will use (1 without OpenMP). */
+int oracle_num_threads(void) {
+#ifdef _OPENMP
+  return omp_get_max_threads();
+#else
+  return 1;
+#endif
+}
+
+void oracle_set_num_threads(int t) {
+#ifdef _OPENMP
+  if (t > 0) omp_set_num_threads(t);
+#else
+  (void)t;
+#endif
+}
