@@ -1,0 +1,237 @@
+/*
+ * kmeans.h -- C ABI of the MI355X (gfx950) mixed-precision Lloyd k-means
+ * library.
+ *
+ * The method is that of Carson, Chen, Liu, "Computing k-means in Mixed
+ * Precision": squared distances d(x,c)^2 = ||x||^2 - 2 x^T c + ||c||^2
+ * (eq:dist-expanded, in its matrix form eq:dist-blas3) are evaluated with the
+ * inputs quantised to a low precision (FP16 or BF16, cross term on the matrix
+ * cores with FP32 accumulation); a per-pair reliability test
+ * (eq:quantis-reliability-test, eq:fallback-rule-mp, Algorithm alg:mp-dist)
+ * flags the pairs whose value may have lost its relative accuracy to
+ * cancellation, and only those are recomputed by the direct formula
+ * (x-c)^T(x-c) (eq:dist-direct) in FP64 from the original FP32 data.  Lloyd's
+ * iteration (Algorithm alg:mp-kmeans) assigns each point to the nearest
+ * centre and replaces each centre by the mean of its points (eq:center).
+ *
+ * Conventions shared by every entry point:
+ *  - Points X are n x d FP32, row-major (point i is the contiguous row
+ *    X[i*d .. i*d+d)); this is the paper's P = [p_1..p_n] in R^{d x n} with
+ *    each column contiguous.  Centres C are k x d FP32 row-major.
+ *  - Unless stated otherwise every array argument is a DEVICE pointer owned
+ *    by the caller (for instance a contiguous PyTorch tensor).  Inputs and
+ *    outputs must not alias.  The library never frees or keeps them.
+ *  - `stream` is a hipStream_t (NULL = the legacy default stream).  All work
+ *    is enqueued on it; a call returns once the work is enqueued unless the
+ *    KM_SYNC flag is set or a host-side `km_stats*` is passed, in which cases
+ *    it returns after the stream has drained.
+ *  - Argument errors are reported synchronously and nothing is enqueued.
+ *    Data-dependent errors (non-finite input, FP16 overflow) are known only
+ *    after the device work ran: they are returned when the call waits for the
+ *    stream (KM_SYNC or stats != NULL) and stored in stats->data_status.
+ *  - Nothing throws across this ABI, nothing aborts, nothing prints.
+ *  - A context is used by one host thread at a time.  The server functions
+ *    (kmeans_submit, kmeans_poll, kmeans_cancel) are thread-safe.
+ */
+#ifndef KMEANS_MI355X_H
+#define KMEANS_MI355X_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes -------------------------------------------------------- */
+enum {
+  KM_OK = 0,
+  KM_PENDING = 1,          /* kmeans_poll: request not finished yet          */
+  KM_ERR_ARG = -1,         /* invalid argument (null, sizes, precision)      */
+  KM_ERR_RANGE = -2,       /* an input overflows the low format (FP16 |v|>=65520) */
+  KM_ERR_NONFINITE = -3,   /* NaN or Inf in X or C                           */
+  KM_ERR_OOM = -4,         /* device allocation failed / over the HBM budget */
+  KM_ERR_DEVICE = -5,      /* a HIP runtime call failed                      */
+  KM_ERR_NOTFOUND = -6,    /* unknown ticket                                 */
+  KM_ERR_CANCELLED = -7,   /* request cancelled                              */
+  KM_ERR_UNSUPPORTED = -8  /* shape outside what the kernels support         */
+};
+
+/* ---- precision ------------------------------------------------------------ */
+/* Low precision of the expanded formula (the paper's u_l). */
+enum {
+  KM_LOW_FP16 = 0,  /* binary16 inputs, FP32 accumulation (MFMA f16)        */
+  KM_LOW_BF16 = 1,  /* bfloat16 inputs, FP32 accumulation (MFMA bf16)       */
+  KM_LOW_FP32 = 2,  /* FP32 inputs, FP32 accumulation (MFMA f32)            */
+  KM_EXACT64 = 3    /* no expanded formula: every pair by the FP64 direct
+                       formula (the plain FP64 baseline kernel)             */
+};
+
+/* How the threshold alpha of the test  d^ > alpha (||x~||^2 + ||c~||^2)  is
+ * chosen.  With gamma = gamma_{d+2}(u_l) = (d+2)u_l / (1-(d+2)u_l):          */
+enum {
+  KM_ALPHA_PAPER_EQ = 0,  /* alpha = 2 rho gamma: E^l of Section 4.3 with the
+                             test eq:quantis-reliability-test (default)      */
+  KM_ALPHA_PAPER_ALG = 1, /* alpha = rho gamma: the listing alg:mp-dist      */
+  KM_ALPHA_EXPLICIT = 2,  /* alpha = km_precision.alpha (>= 0)               */
+  KM_ALPHA_NONE = 3       /* no fallback: uniform low-precision expanded
+                             formula (the paper's "FP16"/"BF16"/"FP32" rows) */
+};
+/* If (d+2) u_l >= 1 gamma is undefined and every pair is corrected. */
+
+typedef struct km_precision {
+  int32_t low;        /* KM_LOW_* or KM_EXACT64                              */
+  int32_t alpha_mode; /* KM_ALPHA_*                                          */
+  double rho;         /* safety factor rho~ (> 2 in the paper modes; 5 by
+                         default, Section 6.1)                              */
+  double alpha;       /* used with KM_ALPHA_EXPLICIT only                   */
+} km_precision;
+/* A NULL km_precision* means {KM_LOW_FP16, KM_ALPHA_PAPER_EQ, 5.0, 0}. */
+
+typedef struct km_stats {
+  int64_t n_corrected; /* pairs recomputed by the FP64 direct formula; the
+                          fallback ratio eta of eq:eta is n_corrected/n_pairs */
+  int64_t n_pairs;     /* pairs evaluated (n*k per assignment pass)          */
+  int32_t iters;       /* Lloyd update rounds performed                      */
+  int32_t data_status; /* KM_OK, KM_ERR_RANGE or KM_ERR_NONFINITE            */
+  double sse_last;     /* SSE (eq:sse) of the last assignment                */
+  double shift_last;   /* max_j ||c_j^t - c_j^{t-1}|| of the last update     */
+  double alpha_used;   /* threshold applied (as rounded to FP32); -1 = none  */
+} km_stats;
+
+/* Flags */
+#define KM_SYNC 1u /* wait for the stream before returning */
+
+typedef struct km_context km_context;
+typedef struct km_server km_server;
+
+/* One k-means problem.  In kmeans_solve_batch every pointer is a device
+ * pointer; in kmeans_submit every pointer is a HOST pointer that must stay
+ * valid until kmeans_poll reports completion or the request is cancelled. */
+typedef struct km_problem {
+  const float *X;   /* n x d points                                          */
+  int64_t n;
+  int32_t d;
+  int32_t k;
+  float *C_inout;   /* k x d: initial centres in, final centres out          */
+  int32_t *labels;  /* n: final assignment                                   */
+  float *mindist;   /* n, nullable: squared distance to the assigned centre */
+  double *sse_hist; /* max_iter+1, nullable: SSE of every assignment pass   */
+  int32_t max_iter; /* t_max                                                 */
+  double tol;       /* tau: stop when the largest centre move is < tol       */
+  km_stats *stats;  /* HOST pointer, nullable: filled on completion          */
+} km_problem;
+
+/* ---- context ---------------------------------------------------------------
+ * Creates a context bound to HIP device `device`: it owns the library's
+ * device workspace (grown on demand) and the tile-shape cache.  Returns
+ * KM_ERR_DEVICE if the device is not a gfx950 GPU. */
+int32_t kmeans_context_create(int32_t device, km_context **out);
+int32_t kmeans_context_destroy(km_context *ctx);
+
+/* ---- one assignment pass ----------------------------------------------------
+ * For every point x_i and centre c_j computes the mixed-precision squared
+ * distance of Algorithm alg:mp-dist (expanded formula on quantised inputs,
+ * reliability test, FP64 direct correction of flagged pairs, result in FP32)
+ * and assigns x_i to the centre with the smallest value (first index among
+ * equal values of the expanded-formula term; Algorithm alg:mp-kmeans).
+ * Outputs:
+ *   labels  [n] int32
+ *   mindist [n] FP32, nullable: ||x_i - c_{label_i}||^2 recomputed in FP64 by
+ *           the direct formula from the FP32 data and rounded once to FP32
+ *   sse     [1] FP64 device scalar, nullable: sum of those FP64 distances
+ *   stats   host, nullable (forces a wait): counts, alpha, data status
+ * Limits: 1 <= d <= 256, 1 <= k <= 65536, 1 <= n.  k > n is allowed. */
+int32_t kmeans_assign(km_context *ctx, const float *X, int64_t n, int32_t d,
+                      const float *C, int32_t k, const km_precision *prec,
+                      int32_t *labels, float *mindist, double *sse,
+                      km_stats *stats, void *stream, uint32_t flags);
+
+/* ---- one centre update (eq:center, Algorithm alg:mp-kmeans) -----------------
+ * C_new[j] = fl32( (sum_{i: labels_i = j} x_i) / m_j ) with the sums taken in
+ * FP64 in a fixed order that does not depend on the launch (points of a
+ * cluster in ascending index, in chunks of 256); an empty cluster keeps
+ * C_old[j].  counts [k] int64 and shift [1] FP64 (max_j ||C_new-C_old||) are
+ * device outputs, nullable.  labels must lie in [0,k). */
+int32_t kmeans_update(km_context *ctx, const float *X, int64_t n, int32_t d,
+                      const int32_t *labels, int32_t k, const float *C_old,
+                      float *C_new, int64_t *counts, double *shift,
+                      void *stream, uint32_t flags);
+
+/* ---- Lloyd's algorithm (Algorithm alg:mp-kmeans) ---------------------------
+ * C_inout holds the initial centres on entry and the final ones on exit.
+ * Runs up to max_iter rounds of (assignment pass, centre update), stopping
+ * after a round whose largest centre move is < tol (tol <= 0: never; a
+ * positive tol costs one device-to-host read per round), then one final
+ * assignment pass whose result fills labels / mindist.  sse_hist (device,
+ * nullable, max_iter+1 entries) receives the SSE of each assignment pass in
+ * order, the final one last.  max_iter = 0 performs the final pass only.
+ * Normalisation of the data (first line of the algorithm) is the caller's. */
+int32_t kmeans_lloyd(km_context *ctx, const float *X, int64_t n, int32_t d,
+                     int32_t k, float *C_inout, int32_t max_iter, double tol,
+                     const km_precision *prec, int32_t *labels, float *mindist,
+                     double *sse_hist, km_stats *stats, void *stream,
+                     uint32_t flags);
+
+/* ---- many independent problems in one set of launches ----------------------
+ * Solves count problems (device pointers) with the same precision.  Each
+ * phase of a Lloyd round is one launch over a work list that spans all
+ * problems, so small problems share the GPU.  Every problem's arithmetic is
+ * identical to a kmeans_lloyd call on it alone (bitwise).  Per-problem tol
+ * stopping is honoured at round granularity. */
+int32_t kmeans_solve_batch(km_context *ctx, km_problem *probs, int32_t count,
+                           const km_precision *prec, void *stream,
+                           uint32_t flags);
+
+/* ---- materialised distances (reports and tests; not on the hot path) -------
+ * D [m x k] FP32: the per-pair value the assignment pass uses (the
+ * expanded-formula value of kept pairs, the FP64 direct value rounded to FP32
+ * for corrected pairs); flagged [m x k] uint8, nullable: 1 where the pair was
+ * corrected.  Same kernels and arithmetic as kmeans_assign. */
+int32_t kmeans_pairwise(km_context *ctx, const float *X, int64_t m, int32_t d,
+                        const float *C, int32_t k, const km_precision *prec,
+                        float *D, uint8_t *flagged, void *stream,
+                        uint32_t flags);
+
+/* ---- quantisation (tests) ---------------------------------------------------
+ * out[i] = bits of the low-precision value of in[i] (round to nearest even,
+ * gradual underflow, overflow to infinity) as used by every kernel; low is
+ * KM_LOW_FP16 or KM_LOW_BF16. */
+int32_t kmeans_quantize(km_context *ctx, const float *in, int64_t count,
+                        int32_t low, uint16_t *out, void *stream,
+                        uint32_t flags);
+
+/* The threshold alpha the library applies for (prec, d); -1 when the mode
+ * has no fallback and +inf when every pair is corrected.  Host only. */
+int32_t kmeans_alpha(const km_precision *prec, int32_t d, double *alpha_out);
+
+/* ---- serving: continuous batching -------------------------------------------
+ * A server owns a device arena of at most hbm_budget_bytes and a scheduler
+ * thread.  kmeans_submit copies nothing yet: the request waits until its
+ * device footprint fits the budget and fewer than max_active requests run,
+ * then its data are copied in and it joins the running set at the next round
+ * boundary.  Every round performs one Lloyd round for all running requests
+ * with batched launches; finished requests are copied back to their host
+ * buffers and leave.  A request's results do not depend on what else runs.
+ * A request whose footprint exceeds the whole budget fails with
+ * KM_ERR_OOM; malformed requests fail with their own error code. */
+int32_t kmeans_server_create(km_context *ctx, size_t hbm_budget_bytes,
+                             int32_t max_active, km_server **out);
+int32_t kmeans_submit(km_server *srv, const km_problem *host_req,
+                      const km_precision *prec, uint64_t *ticket);
+/* KM_OK when done (host buffers filled), KM_PENDING after timeout_ms
+ * (0 = do not wait, < 0 = wait forever), or the request's error code.  A
+ * finished ticket stays queryable until kmeans_server_destroy. */
+int32_t kmeans_poll(km_server *srv, uint64_t ticket, int32_t timeout_ms);
+int32_t kmeans_cancel(km_server *srv, uint64_t ticket);
+/* Waits for the scheduler to finish running requests, cancels queued ones
+ * and frees the arena. */
+int32_t kmeans_server_destroy(km_server *srv);
+
+/* Human-readable text for a status code (static storage). */
+const char *kmeans_status_string(int32_t status);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* KMEANS_MI355X_H */

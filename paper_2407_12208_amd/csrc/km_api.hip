@@ -1,0 +1,781 @@
+// km_api.hip -- the C ABI declared in include/kmeans.h: argument checks,
+// workspace planning and the launch sequences of one assignment pass, one
+// centre update, Lloyd's loop and batched solves.
+#include <math.h>
+#include <string.h>
+
+#include <algorithm>
+#include <new>
+#include <vector>
+
+#include "km_context.hpp"
+
+namespace km {
+
+// ---------------------------------------------------------------------------
+// Uploader
+// ---------------------------------------------------------------------------
+hipError_t Uploader::init(size_t bytes) {
+  hipError_t e = hipHostMalloc(reinterpret_cast<void**>(&host), bytes, hipHostMallocDefault);
+  if (e != hipSuccess) return e;
+  e = hipMalloc(reinterpret_cast<void**>(&dev), bytes);
+  if (e != hipSuccess) {
+    (void)hipHostFree(host);
+    host = nullptr;
+    return e;
+  }
+  cap = bytes;
+  head = 0;
+  return hipSuccess;
+}
+
+void Uploader::destroy() {
+  if (host) (void)hipHostFree(host);
+  if (dev) (void)hipFree(dev);
+  host = dev = nullptr;
+  cap = head = 0;
+}
+
+void* Uploader::put(const void* src, size_t bytes, hipStream_t st) {
+  size_t need = (bytes + 255) & ~size_t(255);
+  if (need > cap) return nullptr;
+  if (head + need > cap) {
+    // wrap: earlier copies out of this ring must have completed before the
+    // host overwrites their source bytes
+    if (hipDeviceSynchronize() != hipSuccess) return nullptr;
+    head = 0;
+  }
+  memcpy(host + head, src, bytes);
+  void* d = dev + head;
+  if (hipMemcpyAsync(d, host + head, bytes, hipMemcpyHostToDevice, st) != hipSuccess) return nullptr;
+  head += need;
+  return d;
+}
+
+// ---------------------------------------------------------------------------
+// Precision and planning
+// ---------------------------------------------------------------------------
+static double unit_roundoff_low(int low) {
+  switch (low) {
+    case kLowFP16: return ldexp(1.0, -11);
+    case kLowBF16: return ldexp(1.0, -8);
+    case kLowFP32: return ldexp(1.0, -24);
+  }
+  return 0.0;
+}
+
+km_precision precision_or_default(const km_precision* p) {
+  if (p) return *p;
+  km_precision q;
+  q.low = KM_LOW_FP16;
+  q.alpha_mode = KM_ALPHA_PAPER_EQ;
+  q.rho = 5.0;
+  q.alpha = 0.0;
+  return q;
+}
+
+int32_t validate_precision(const km_precision& p) {
+  if (p.low < KM_LOW_FP16 || p.low > KM_EXACT64) return KM_ERR_ARG;
+  if (p.low == KM_EXACT64) return KM_OK;
+  if (p.alpha_mode < KM_ALPHA_PAPER_EQ || p.alpha_mode > KM_ALPHA_NONE) return KM_ERR_ARG;
+  if ((p.alpha_mode == KM_ALPHA_PAPER_EQ || p.alpha_mode == KM_ALPHA_PAPER_ALG) && !(p.rho > 2.0))
+    return KM_ERR_ARG;  // the relative bound needs rho~ > 2 (Section 4.3)
+  if (p.alpha_mode == KM_ALPHA_EXPLICIT && !(p.alpha >= 0.0)) return KM_ERR_ARG;
+  return KM_OK;
+}
+
+double alpha_for(const km_precision& p, int d) {
+  if (p.low == KM_EXACT64 || p.alpha_mode == KM_ALPHA_NONE) return -1.0;
+  if (p.alpha_mode == KM_ALPHA_EXPLICIT) return p.alpha;
+  const double mu = (double)(d + 2) * unit_roundoff_low(p.low);
+  if (!(mu < 1.0)) return INFINITY;  // gamma undefined: correct every pair
+  const double g = mu / (1.0 - mu);
+  return p.alpha_mode == KM_ALPHA_PAPER_EQ ? 2.0 * p.rho * g : p.rho * g;
+}
+
+int32_t status_from_bits(int bits) {
+  if (bits & kStatusNonFinite) return KM_ERR_NONFINITE;
+  if (bits & kStatusRange) return KM_ERR_RANGE;
+  if (bits & kStatusBadLabel) return KM_ERR_ARG;  // label out of range in an update
+  return KM_OK;
+}
+
+size_t cq_elem_bytes(int low) { return low == kLowFP32 ? 4 : 2; }
+
+// Above this threshold every pair fails the test (d^ <= 2 S always), so the
+// pass is run by the FP64 direct kernel instead of a fully divergent sweep.
+static constexpr double kDenseAlpha = 2.5;
+
+AssignPlan plan_assign(const km_precision& p, int64_t n, int d, int k) {
+  AssignPlan a{};
+  a.low = p.low;
+  a.DP = padded_dim(d);
+  a.k_pad = (k + 31) & ~31;
+  const double alpha = alpha_for(p, d);
+  a.alpha_used = alpha;
+  if (p.low == KM_EXACT64) {
+    a.route = Route::Direct64Exact;
+  } else if (alpha < 0.0) {
+    a.route = Route::MfmaNoFallback;
+  } else if (!(alpha < kDenseAlpha)) {
+    a.route = Route::Direct64All;
+  } else {
+    a.route = Route::Mfma;
+  }
+  a.alpha_f = alpha < 0.0 ? 0.0f : (float)std::min(alpha, 1e30);
+  a.oma = 1.0f - a.alpha_f;
+  if (a.route == Route::Mfma) a.alpha_used = (double)a.alpha_f;
+  if (a.route == Route::Direct64Exact || a.route == Route::Direct64All)
+    a.nwg = (int)((n + kDirectPointsPerWg - 1) / kDirectPointsPerWg);
+  else
+    a.nwg = (int)((n + mfma_points_per_wg(p.low, a.DP) - 1) / mfma_points_per_wg(p.low, a.DP));
+  return a;
+}
+
+// ---------------------------------------------------------------------------
+// Launch helpers
+// ---------------------------------------------------------------------------
+static std::vector<int32_t> prefix(const std::vector<int>& counts) {
+  std::vector<int32_t> s(counts.size() + 1, 0);
+  for (size_t i = 0; i < counts.size(); ++i) s[i + 1] = s[i] + counts[i];
+  return s;
+}
+
+hipError_t run_prep(km_context_impl* ctx, int low, const std::vector<PrepProb>& probs,
+                    const std::vector<int>& kpads, hipStream_t st) {
+  std::vector<int> wgs(kpads.size());
+  for (size_t i = 0; i < kpads.size(); ++i) wgs[i] = (kpads[i] + 255) / 256;
+  std::vector<int32_t> pre = prefix(wgs);
+  void* dp = ctx->up.put(probs.data(), probs.size() * sizeof(PrepProb), st);
+  void* ds = ctx->up.put(pre.data(), pre.size() * sizeof(int32_t), st);
+  if (!dp || !ds) return hipErrorOutOfMemory;
+  return launch_prep(low, (const PrepProb*)dp, (const int32_t*)ds, (int)probs.size(), pre.back(), st);
+}
+
+hipError_t run_assign(km_context_impl* ctx, const AssignPlan& shape, int mode,
+                      const std::vector<AssignProb>& probs, const std::vector<int>& nwgs, hipStream_t st) {
+  std::vector<int32_t> pre = prefix(nwgs);
+  if (pre.back() == 0) return hipSuccess;
+  void* dp = ctx->up.put(probs.data(), probs.size() * sizeof(AssignProb), st);
+  void* ds = ctx->up.put(pre.data(), pre.size() * sizeof(int32_t), st);
+  if (!dp || !ds) return hipErrorOutOfMemory;
+  switch (shape.route) {
+    case Route::Mfma:
+    case Route::MfmaNoFallback:
+      return launch_assign_mfma(shape.low, shape.DP, mode, shape.route == Route::Mfma,
+                                (const AssignProb*)dp, (const int32_t*)ds, (int)probs.size(), pre.back(), st);
+    case Route::Direct64Exact:
+    case Route::Direct64All:
+      return launch_assign_direct64(shape.route == Route::Direct64Exact, mode, (const AssignProb*)dp,
+                                    (const int32_t*)ds, (int)probs.size(), pre.back(), st);
+  }
+  return hipErrorInvalidValue;
+}
+
+hipError_t run_reduce(km_context_impl* ctx, const std::vector<ReduceProb>& probs, hipStream_t st) {
+  void* dp = ctx->up.put(probs.data(), probs.size() * sizeof(ReduceProb), st);
+  if (!dp) return hipErrorOutOfMemory;
+  return launch_reduce_parts((const ReduceProb*)dp, (int)probs.size(), st);
+}
+
+void plan_update(Plan& pl, int64_t n, int d, int k) {
+  const int ntiles = (int)((n + kUpdTile - 1) / kUpdTile);
+  pl.add<int32_t>((size_t)k * ntiles);  // hist
+  pl.add<int32_t>((size_t)k * ntiles);  // offs
+  pl.add<int32_t>((size_t)n);           // perm
+  pl.add<int32_t>((size_t)k + 1);       // cstart
+  pl.add<int32_t>((size_t)k + 1);       // chunk_start
+  pl.add<double>(((size_t)(n + kUpdChunk - 1) / kUpdChunk + k) * d);  // chunk sums
+  pl.add<double>((size_t)k);            // shift2
+}
+
+UpdateProb carve_update(Arena& a, int64_t n, int d, int k) {
+  UpdateProb u{};
+  const int ntiles = (int)((n + kUpdTile - 1) / kUpdTile);
+  u.hist = a.take<int32_t>((size_t)k * ntiles);
+  u.offs = a.take<int32_t>((size_t)k * ntiles);
+  u.perm = a.take<int32_t>((size_t)n);
+  u.cstart = a.take<int32_t>((size_t)k + 1);
+  u.chunk_start = a.take<int32_t>((size_t)k + 1);
+  u.chunk_sum = a.take<double>(((size_t)(n + kUpdChunk - 1) / kUpdChunk + k) * d);
+  u.shift2 = a.take<double>((size_t)k);
+  u.n = n;
+  u.d = d;
+  u.k = k;
+  u.ntiles = ntiles;
+  return u;
+}
+
+hipError_t run_update(km_context_impl* ctx, const std::vector<UpdateProb>& probs, hipStream_t st) {
+  const int np = (int)probs.size();
+  std::vector<int> tiles(np), cl(np), chunkwg(np), clwg(np);
+  for (int i = 0; i < np; ++i) {
+    tiles[i] = probs[i].ntiles;
+    cl[i] = probs[i].k;
+    chunkwg[i] = (int)(((probs[i].n + kUpdChunk - 1) / kUpdChunk + probs[i].k + 3) / 4);
+    clwg[i] = (probs[i].k + 3) / 4;
+  }
+  std::vector<int32_t> pre;
+  for (auto* v : {&tiles, &cl, &chunkwg, &clwg}) {
+    std::vector<int32_t> p = prefix(*v);
+    pre.insert(pre.end(), p.begin(), p.end());
+  }
+  void* dp = ctx->up.put(probs.data(), probs.size() * sizeof(UpdateProb), st);
+  void* ds = ctx->up.put(pre.data(), pre.size() * sizeof(int32_t), st);
+  if (!dp || !ds) return hipErrorOutOfMemory;
+  return launch_update((const UpdateProb*)dp, probs.data(), np, (const int32_t*)ds, st);
+}
+
+}  // namespace km
+
+using namespace km;
+
+// ---------------------------------------------------------------------------
+// C ABI
+// ---------------------------------------------------------------------------
+#define KM_HIP(call)                         \
+  do {                                       \
+    hipError_t e_ = (call);                  \
+    if (e_ != hipSuccess) {                  \
+      (void)hipGetLastError();               \
+      return e_ == hipErrorOutOfMemory ? KM_ERR_OOM : KM_ERR_DEVICE; \
+    }                                        \
+  } while (0)
+
+extern "C" {
+
+const char* kmeans_status_string(int32_t s) {
+  switch (s) {
+    case KM_OK: return "ok";
+    case KM_PENDING: return "pending";
+    case KM_ERR_ARG: return "invalid argument";
+    case KM_ERR_RANGE: return "input overflows the low-precision format";
+    case KM_ERR_NONFINITE: return "non-finite input";
+    case KM_ERR_OOM: return "out of device memory or over the memory budget";
+    case KM_ERR_DEVICE: return "HIP runtime error";
+    case KM_ERR_NOTFOUND: return "unknown ticket";
+    case KM_ERR_CANCELLED: return "cancelled";
+    case KM_ERR_UNSUPPORTED: return "unsupported shape";
+  }
+  return "unknown status";
+}
+
+int32_t kmeans_alpha(const km_precision* prec, int32_t d, double* alpha_out) {
+  if (!alpha_out || d < 1) return KM_ERR_ARG;
+  km_precision p = precision_or_default(prec);
+  int32_t v = validate_precision(p);
+  if (v != KM_OK) return v;
+  double a = alpha_for(p, d);
+  if (p.low != KM_EXACT64 && a >= 0.0 && a < 2.5 && p.alpha_mode != KM_ALPHA_NONE) a = (double)(float)a;
+  *alpha_out = a;
+  return KM_OK;
+}
+
+int32_t kmeans_context_create(int32_t device, km_context** out) {
+  if (!out) return KM_ERR_ARG;
+  *out = nullptr;
+  int count = 0;
+  if (hipGetDeviceCount(&count) != hipSuccess || device < 0 || device >= count) return KM_ERR_DEVICE;
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, device) != hipSuccess) return KM_ERR_DEVICE;
+  if (strncmp(prop.gcnArchName, "gfx950", 6) != 0) return KM_ERR_DEVICE;
+  if (hipSetDevice(device) != hipSuccess) return KM_ERR_DEVICE;
+  km_context* c = new (std::nothrow) km_context();
+  if (!c) return KM_ERR_OOM;
+  c->device = device;
+  c->num_cu = prop.multiProcessorCount;
+  if (c->up.init(8u << 20) != hipSuccess ||
+      hipHostMalloc(reinterpret_cast<void**>(&c->h_scalar), 64, hipHostMallocDefault) != hipSuccess ||
+      hipHostMalloc(reinterpret_cast<void**>(&c->h_result), sizeof(KResult) * km_context_impl::kMaxResults,
+                    hipHostMallocDefault) != hipSuccess) {
+    kmeans_context_destroy(c);
+    return KM_ERR_OOM;
+  }
+  *out = c;
+  return KM_OK;
+}
+
+int32_t kmeans_context_destroy(km_context* c) {
+  if (!c) return KM_ERR_ARG;
+  (void)hipSetDevice(c->device);
+  (void)hipDeviceSynchronize();
+  c->up.destroy();
+  if (c->arena.base) (void)hipFree(c->arena.base);
+  if (c->h_scalar) (void)hipHostFree(c->h_scalar);
+  if (c->h_result) (void)hipHostFree(c->h_result);
+  delete c;
+  return KM_OK;
+}
+
+}  // extern "C"
+
+namespace km {
+
+static int32_t check_shape(int64_t n, int32_t d, int32_t k, const km_precision& p) {
+  if (n < 1 || n > (int64_t)INT32_MAX - 1024 || d < 1 || k < 1 || k > 65536) return KM_ERR_ARG;
+  if (p.low != KM_EXACT64) {
+    const int DP = padded_dim(d);
+    if (DP < 0) return KM_ERR_UNSUPPORTED;
+    if (p.low == KM_LOW_FP32 && DP > 128) return KM_ERR_UNSUPPORTED;
+  }
+  return KM_OK;
+}
+
+// Everything one assignment pass of one problem needs on the device.
+struct PassBufs {
+  void* Cq;
+  float* cinit;
+  float* ca;
+  double* sse_part;
+  unsigned long long* corr_part;
+  int* status;
+  KResult* result;
+};
+
+static void plan_pass(Plan& pl, const AssignPlan& a) {
+  pl.add<char>((size_t)a.k_pad * a.DP * 4);
+  pl.add<float>(a.k_pad);
+  pl.add<float>(a.k_pad);
+  pl.add<double>(a.nwg);
+  pl.add<unsigned long long>(a.nwg);
+  pl.add<int>(1);
+  pl.add<KResult>(1);
+}
+
+static PassBufs carve_pass(Arena& ar, const AssignPlan& a) {
+  PassBufs b;
+  b.Cq = ar.take<char>((size_t)a.k_pad * a.DP * 4);
+  b.cinit = ar.take<float>(a.k_pad);
+  b.ca = ar.take<float>(a.k_pad);
+  b.sse_part = ar.take<double>(a.nwg);
+  b.corr_part = ar.take<unsigned long long>(a.nwg);
+  b.status = ar.take<int>(1);
+  b.result = ar.take<KResult>(1);
+  return b;
+}
+
+static bool uses_prep(const AssignPlan& a) { return a.route == Route::Mfma || a.route == Route::MfmaNoFallback; }
+
+// Enqueue one assignment pass (prep + assign + reduce) of one problem.
+static hipError_t enqueue_pass(km_context_impl* ctx, const AssignPlan& a, const PassBufs& b,
+                               const float* X, int64_t n, int d, const float* C, int k, int32_t* labels,
+                               float* mindist, double* sse_slot, int mode, float* D, uint8_t* flagged,
+                               hipStream_t st) {
+  if (uses_prep(a)) {
+    PrepProb pp{};
+    pp.C = C;
+    pp.Cq = b.Cq;
+    pp.cinit = b.cinit;
+    pp.ca = b.ca;
+    pp.status = b.status;
+    pp.alpha = a.alpha_f;
+    pp.k = k;
+    pp.k_pad = a.k_pad;
+    pp.d = d;
+    pp.DP = a.DP;
+    hipError_t e = run_prep(ctx, a.low, {pp}, {a.k_pad}, st);
+    if (e != hipSuccess) return e;
+  }
+  AssignProb ap{};
+  ap.X = X;
+  ap.C = C;
+  ap.Cq = b.Cq;
+  ap.cinit = b.cinit;
+  ap.ca = b.ca;
+  ap.labels = labels;
+  ap.mindist = mindist;
+  ap.D = D;
+  ap.flagged = flagged;
+  ap.sse_part = b.sse_part;
+  ap.corr_part = b.corr_part;
+  ap.status = b.status;
+  ap.n = n;
+  ap.d = d;
+  ap.k = k;
+  ap.k_pad = a.k_pad;
+  ap.oma = a.oma;
+  hipError_t e = run_assign(ctx, a, mode, {ap}, {a.nwg}, st);
+  if (e != hipSuccess) return e;
+  ReduceProb rp{};
+  rp.sse_part = b.sse_part;
+  rp.corr_part = b.corr_part;
+  rp.status = b.status;
+  rp.sse_out = sse_slot;
+  rp.result = b.result;
+  rp.pairs = n * (long long)k;
+  rp.nparts = a.nwg;
+  return run_reduce(ctx, {rp}, st);
+}
+
+static int32_t finish_stats(km_context_impl* ctx, const KResult* dres, km_stats* stats, const AssignPlan& a,
+                            int32_t iters, hipStream_t st) {
+  KM_HIP(hipMemcpyAsync(ctx->h_result, dres, sizeof(KResult), hipMemcpyDeviceToHost, st));
+  KM_HIP(hipStreamSynchronize(st));
+  const KResult r = *ctx->h_result;
+  const int32_t ds = status_from_bits(r.status);
+  if (stats) {
+    stats->n_corrected = a.route == Route::Direct64Exact ? 0 : r.n_corrected;
+    stats->n_pairs = r.n_pairs;
+    stats->iters = iters;
+    stats->data_status = ds;
+    stats->sse_last = r.sse;
+    stats->shift_last = r.shift;
+    stats->alpha_used = a.alpha_used;
+  }
+  return ds;
+}
+
+}  // namespace km
+
+extern "C" {
+
+int32_t kmeans_assign(km_context* ctx, const float* X, int64_t n, int32_t d, const float* C, int32_t k,
+                      const km_precision* prec, int32_t* labels, float* mindist, double* sse,
+                      km_stats* stats, void* stream, uint32_t flags) {
+  if (!ctx || !X || !C || !labels) return KM_ERR_ARG;
+  km_precision p = precision_or_default(prec);
+  int32_t v = validate_precision(p);
+  if (v != KM_OK) return v;
+  v = check_shape(n, d, k, p);
+  if (v != KM_OK) return v;
+  hipStream_t st = (hipStream_t)stream;
+  KM_HIP(hipSetDevice(ctx->device));
+  AssignPlan a = plan_assign(p, n, d, k);
+  Plan pl;
+  plan_pass(pl, a);
+  KM_HIP(ctx->arena.ensure(pl.bytes));
+  ctx->arena.reset();
+  PassBufs b = carve_pass(ctx->arena, a);
+  KM_HIP(hipMemsetAsync(b.status, 0, sizeof(int), st));
+  KM_HIP(hipMemsetAsync(b.result, 0, sizeof(KResult), st));
+  KM_HIP(enqueue_pass(ctx, a, b, X, n, d, C, k, labels, mindist, sse, 0, nullptr, nullptr, st));
+  if (stats || (flags & KM_SYNC)) return finish_stats(ctx, b.result, stats, a, 0, st);
+  return KM_OK;
+}
+
+int32_t kmeans_pairwise(km_context* ctx, const float* X, int64_t m, int32_t d, const float* C, int32_t k,
+                        const km_precision* prec, float* D, uint8_t* flagged, void* stream, uint32_t flags) {
+  if (!ctx || !X || !C || !D) return KM_ERR_ARG;
+  km_precision p = precision_or_default(prec);
+  int32_t v = validate_precision(p);
+  if (v != KM_OK) return v;
+  v = check_shape(m, d, k, p);
+  if (v != KM_OK) return v;
+  hipStream_t st = (hipStream_t)stream;
+  KM_HIP(hipSetDevice(ctx->device));
+  AssignPlan a = plan_assign(p, m, d, k);
+  Plan pl;
+  plan_pass(pl, a);
+  KM_HIP(ctx->arena.ensure(pl.bytes));
+  ctx->arena.reset();
+  PassBufs b = carve_pass(ctx->arena, a);
+  KM_HIP(hipMemsetAsync(b.status, 0, sizeof(int), st));
+  KM_HIP(hipMemsetAsync(b.result, 0, sizeof(KResult), st));
+  KM_HIP(enqueue_pass(ctx, a, b, X, m, d, C, k, nullptr, nullptr, nullptr, 1, D, flagged, st));
+  if (flags & KM_SYNC) return finish_stats(ctx, b.result, nullptr, a, 0, st);
+  return KM_OK;
+}
+
+int32_t kmeans_quantize(km_context* ctx, const float* in, int64_t count, int32_t low, uint16_t* out,
+                        void* stream, uint32_t flags) {
+  if (!ctx || !in || !out || count < 0 || (low != KM_LOW_FP16 && low != KM_LOW_BF16)) return KM_ERR_ARG;
+  hipStream_t st = (hipStream_t)stream;
+  KM_HIP(hipSetDevice(ctx->device));
+  KM_HIP(launch_quantize(low, in, count, out, st));
+  if (flags & KM_SYNC) KM_HIP(hipStreamSynchronize(st));
+  return KM_OK;
+}
+
+int32_t kmeans_update(km_context* ctx, const float* X, int64_t n, int32_t d, const int32_t* labels, int32_t k,
+                      const float* C_old, float* C_new, int64_t* counts, double* shift, void* stream,
+                      uint32_t flags) {
+  if (!ctx || !X || !labels || !C_old || !C_new || C_old == C_new) return KM_ERR_ARG;
+  if (n < 1 || n > (int64_t)INT32_MAX - 1024 || d < 1 || k < 1 || k > 65536) return KM_ERR_ARG;
+  hipStream_t st = (hipStream_t)stream;
+  KM_HIP(hipSetDevice(ctx->device));
+  Plan pl;
+  plan_update(pl, n, d, k);
+  pl.add<int>(1);
+  pl.add<KResult>(1);
+  KM_HIP(ctx->arena.ensure(pl.bytes));
+  ctx->arena.reset();
+  UpdateProb u = carve_update(ctx->arena, n, d, k);
+  int* status = ctx->arena.take<int>(1);
+  KResult* res = ctx->arena.take<KResult>(1);
+  KM_HIP(hipMemsetAsync(status, 0, sizeof(int), st));
+  KM_HIP(hipMemsetAsync(res, 0, sizeof(KResult), st));
+  u.X = X;
+  u.labels = labels;
+  u.C_old = C_old;
+  u.C_new = C_new;
+  u.counts_out = reinterpret_cast<long long*>(counts);
+  u.shift_out = shift;
+  u.result = res;
+  u.status = status;
+  KM_HIP(run_update(ctx, {u}, st));
+  if (flags & KM_SYNC) {
+    KM_HIP(hipMemcpyAsync(ctx->h_result, status, sizeof(int), hipMemcpyDeviceToHost, st));
+    KM_HIP(hipStreamSynchronize(st));
+    return status_from_bits(*reinterpret_cast<int*>(ctx->h_result));
+  }
+  return KM_OK;
+}
+
+int32_t kmeans_lloyd(km_context* ctx, const float* X, int64_t n, int32_t d, int32_t k, float* C_inout,
+                     int32_t max_iter, double tol, const km_precision* prec, int32_t* labels, float* mindist,
+                     double* sse_hist, km_stats* stats, void* stream, uint32_t flags) {
+  if (!ctx || !X || !C_inout || !labels || max_iter < 0) return KM_ERR_ARG;
+  km_precision p = precision_or_default(prec);
+  int32_t v = validate_precision(p);
+  if (v != KM_OK) return v;
+  v = check_shape(n, d, k, p);
+  if (v != KM_OK) return v;
+  hipStream_t st = (hipStream_t)stream;
+  KM_HIP(hipSetDevice(ctx->device));
+  AssignPlan a = plan_assign(p, n, d, k);
+  Plan pl;
+  plan_pass(pl, a);
+  plan_update(pl, n, d, k);
+  pl.add<float>((size_t)k * d);  // second centre buffer
+  KM_HIP(ctx->arena.ensure(pl.bytes));
+  ctx->arena.reset();
+  PassBufs b = carve_pass(ctx->arena, a);
+  UpdateProb u = carve_update(ctx->arena, n, d, k);
+  float* Cw = ctx->arena.take<float>((size_t)k * d);
+  KM_HIP(hipMemsetAsync(b.status, 0, sizeof(int), st));
+  KM_HIP(hipMemsetAsync(b.result, 0, sizeof(KResult), st));
+  u.X = X;
+  u.labels = labels;
+  u.result = b.result;
+  u.status = b.status;
+  float* cur = C_inout;
+  float* nxt = Cw;
+  int32_t it = 0;
+  for (; it < max_iter; ++it) {
+    KM_HIP(enqueue_pass(ctx, a, b, X, n, d, cur, k, labels, nullptr, sse_hist ? sse_hist + it : nullptr, 0,
+                        nullptr, nullptr, st));
+    u.C_old = cur;
+    u.C_new = nxt;
+    KM_HIP(run_update(ctx, {u}, st));
+    std::swap(cur, nxt);
+    if (tol > 0.0) {
+      KM_HIP(hipMemcpyAsync(ctx->h_scalar, &b.result->shift, sizeof(double), hipMemcpyDeviceToHost, st));
+      KM_HIP(hipStreamSynchronize(st));
+      if (*ctx->h_scalar < tol) {
+        ++it;
+        break;
+      }
+    }
+  }
+  KM_HIP(enqueue_pass(ctx, a, b, X, n, d, cur, k, labels, mindist, sse_hist ? sse_hist + it : nullptr, 0,
+                      nullptr, nullptr, st));
+  if (cur != C_inout)
+    KM_HIP(hipMemcpyAsync(C_inout, cur, sizeof(float) * (size_t)k * d, hipMemcpyDeviceToDevice, st));
+  if (stats || (flags & KM_SYNC)) return finish_stats(ctx, b.result, stats, a, it, st);
+  return KM_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Batched solves
+// ---------------------------------------------------------------------------
+namespace km {
+
+struct BatchState {
+  km_problem* prob;
+  AssignPlan plan;
+  PassBufs bufs;
+  UpdateProb upd;
+  float* cur;
+  float* nxt;
+  int32_t it = 0;
+  bool done = false;  // update rounds finished (converged or max_iter)
+};
+
+// Enqueue one assignment pass for every listed problem: one prep launch per
+// low format, one assignment launch per (route, DP) group, one reduce launch.
+static hipError_t enqueue_batch_pass(km_context_impl* ctx, std::vector<BatchState*>& list, bool final_pass,
+                                     hipStream_t st) {
+  if (list.empty()) return hipSuccess;
+  // prep
+  {
+    std::vector<PrepProb> pp;
+    std::vector<int> kp;
+    int low = -1;
+    for (BatchState* s : list) {
+      if (!uses_prep(s->plan)) continue;
+      PrepProb q{};
+      q.C = s->cur;
+      q.Cq = s->bufs.Cq;
+      q.cinit = s->bufs.cinit;
+      q.ca = s->bufs.ca;
+      q.status = s->bufs.status;
+      q.alpha = s->plan.alpha_f;
+      q.k = s->prob->k;
+      q.k_pad = s->plan.k_pad;
+      q.d = s->prob->d;
+      q.DP = s->plan.DP;
+      pp.push_back(q);
+      kp.push_back(s->plan.k_pad);
+      low = s->plan.low;
+    }
+    if (!pp.empty()) {
+      hipError_t e = run_prep(ctx, low, pp, kp, st);
+      if (e != hipSuccess) return e;
+    }
+  }
+  // assign, grouped by kernel shape
+  std::vector<bool> taken(list.size(), false);
+  for (size_t i = 0; i < list.size(); ++i) {
+    if (taken[i]) continue;
+    const AssignPlan& sh = list[i]->plan;
+    std::vector<AssignProb> ap;
+    std::vector<int> nw;
+    for (size_t j = i; j < list.size(); ++j) {
+      const AssignPlan& o = list[j]->plan;
+      if (taken[j] || o.route != sh.route || o.DP != sh.DP || o.low != sh.low) continue;
+      taken[j] = true;
+      BatchState* s = list[j];
+      AssignProb a{};
+      a.X = s->prob->X;
+      a.C = s->cur;
+      a.Cq = s->bufs.Cq;
+      a.cinit = s->bufs.cinit;
+      a.ca = s->bufs.ca;
+      a.labels = s->prob->labels;
+      a.mindist = final_pass ? s->prob->mindist : nullptr;
+      a.sse_part = s->bufs.sse_part;
+      a.corr_part = s->bufs.corr_part;
+      a.status = s->bufs.status;
+      a.n = s->prob->n;
+      a.d = s->prob->d;
+      a.k = s->prob->k;
+      a.k_pad = o.k_pad;
+      a.oma = o.oma;
+      ap.push_back(a);
+      nw.push_back(o.nwg);
+    }
+    hipError_t e = run_assign(ctx, sh, 0, ap, nw, st);
+    if (e != hipSuccess) return e;
+  }
+  // reduce
+  std::vector<ReduceProb> rp;
+  for (BatchState* s : list) {
+    ReduceProb r{};
+    r.sse_part = s->bufs.sse_part;
+    r.corr_part = s->bufs.corr_part;
+    r.status = s->bufs.status;
+    r.sse_out = s->prob->sse_hist ? s->prob->sse_hist + s->it : nullptr;
+    r.result = s->bufs.result;
+    r.pairs = s->prob->n * (long long)s->prob->k;
+    r.nparts = s->plan.nwg;
+    rp.push_back(r);
+  }
+  return run_reduce(ctx, rp, st);
+}
+
+}  // namespace km
+
+extern "C" int32_t kmeans_solve_batch(km_context* ctx, km_problem* probs, int32_t count,
+                                      const km_precision* prec, void* stream, uint32_t flags) {
+  if (!ctx || (!probs && count > 0) || count < 0) return KM_ERR_ARG;
+  if (count == 0) return KM_OK;
+  if (count > km_context_impl::kMaxResults) return KM_ERR_ARG;
+  km_precision p = precision_or_default(prec);
+  int32_t v = validate_precision(p);
+  if (v != KM_OK) return v;
+  for (int i = 0; i < count; ++i) {
+    const km_problem& q = probs[i];
+    if (!q.X || !q.C_inout || !q.labels || q.max_iter < 0) return KM_ERR_ARG;
+    v = check_shape(q.n, q.d, q.k, p);
+    if (v != KM_OK) return v;
+  }
+  hipStream_t st = (hipStream_t)stream;
+  KM_HIP(hipSetDevice(ctx->device));
+  std::vector<BatchState> S(count);
+  Plan pl;
+  for (int i = 0; i < count; ++i) {
+    S[i].prob = &probs[i];
+    S[i].plan = plan_assign(p, probs[i].n, probs[i].d, probs[i].k);
+    plan_pass(pl, S[i].plan);
+    plan_update(pl, probs[i].n, probs[i].d, probs[i].k);
+    pl.add<float>((size_t)probs[i].k * probs[i].d);
+  }
+  KM_HIP(ctx->arena.ensure(pl.bytes));
+  ctx->arena.reset();
+  KResult* results = nullptr;
+  for (int i = 0; i < count; ++i) {
+    BatchState& s = S[i];
+    s.bufs = carve_pass(ctx->arena, s.plan);
+    s.upd = carve_update(ctx->arena, s.prob->n, s.prob->d, s.prob->k);
+    s.nxt = ctx->arena.take<float>((size_t)s.prob->k * s.prob->d);
+    s.cur = s.prob->C_inout;
+    s.upd.X = s.prob->X;
+    s.upd.labels = s.prob->labels;
+    s.upd.result = s.bufs.result;
+    s.upd.status = s.bufs.status;
+    KM_HIP(hipMemsetAsync(s.bufs.status, 0, sizeof(int), st));
+    KM_HIP(hipMemsetAsync(s.bufs.result, 0, sizeof(KResult), st));
+    s.done = s.prob->max_iter == 0;
+  }
+  (void)results;
+  bool need_tol = false;
+  for (int i = 0; i < count; ++i) need_tol |= probs[i].tol > 0.0;
+  for (;;) {
+    std::vector<BatchState*> act;
+    for (auto& s : S)
+      if (!s.done) act.push_back(&s);
+    if (act.empty()) break;
+    KM_HIP(enqueue_batch_pass(ctx, act, false, st));
+    std::vector<UpdateProb> up;
+    for (BatchState* s : act) {
+      s->upd.C_old = s->cur;
+      s->upd.C_new = s->nxt;
+      up.push_back(s->upd);
+    }
+    KM_HIP(run_update(ctx, up, st));
+    for (BatchState* s : act) {
+      std::swap(s->cur, s->nxt);
+      s->it += 1;
+      if (s->it >= s->prob->max_iter) s->done = true;
+    }
+    if (need_tol) {
+      for (size_t i = 0; i < act.size(); ++i)
+        KM_HIP(hipMemcpyAsync(ctx->h_result + i, act[i]->bufs.result, sizeof(KResult), hipMemcpyDeviceToHost, st));
+      KM_HIP(hipStreamSynchronize(st));
+      for (size_t i = 0; i < act.size(); ++i)
+        if (act[i]->prob->tol > 0.0 && ctx->h_result[i].shift < act[i]->prob->tol) act[i]->done = true;
+    }
+  }
+  std::vector<BatchState*> all;
+  for (auto& s : S) all.push_back(&s);
+  KM_HIP(enqueue_batch_pass(ctx, all, true, st));
+  for (auto& s : S)
+    if (s.cur != s.prob->C_inout)
+      KM_HIP(hipMemcpyAsync(s.prob->C_inout, s.cur, sizeof(float) * (size_t)s.prob->k * s.prob->d,
+                            hipMemcpyDeviceToDevice, st));
+  bool want_stats = (flags & KM_SYNC) != 0;
+  for (int i = 0; i < count; ++i) want_stats |= probs[i].stats != nullptr;
+  if (!want_stats) return KM_OK;
+  for (int i = 0; i < count; ++i)
+    KM_HIP(hipMemcpyAsync(ctx->h_result + i, S[i].bufs.result, sizeof(KResult), hipMemcpyDeviceToHost, st));
+  KM_HIP(hipStreamSynchronize(st));
+  int32_t first_err = KM_OK;
+  for (int i = 0; i < count; ++i) {
+    const KResult r = ctx->h_result[i];
+    const int32_t ds = status_from_bits(r.status);
+    if (ds != KM_OK && first_err == KM_OK) first_err = ds;
+    if (probs[i].stats) {
+      km_stats* o = probs[i].stats;
+      o->n_corrected = S[i].plan.route == Route::Direct64Exact ? 0 : r.n_corrected;
+      o->n_pairs = r.n_pairs;
+      o->iters = S[i].it;
+      o->data_status = ds;
+      o->sse_last = r.sse;
+      o->shift_last = r.shift;
+      o->alpha_used = S[i].plan.alpha_used;
+    }
+  }
+  return first_err;
+}

@@ -1,0 +1,679 @@
+// km_assign.hip -- assignment-pass kernels for gfx950.
+//
+//  k_prep_centroids  quantises the centres (round to nearest even) into a
+//                    dense [k_pad x DP] low-precision array and forms the
+//                    per-centre constants of the fused epilogue.
+//  k_assign_mfma     one workgroup per tile of points: each lane loads its
+//                    matrix-core fragments of the FP32 points once from HBM,
+//                    rounds them to the low format and keeps them in
+//                    registers for the whole sweep over all centres
+//                    (double-buffered LDS tiles) with 32x32 MFMAs, and fuses
+//                    the expanded formula, the reliability test, the FP64
+//                    direct correction of flagged pairs, the argmin, the FP64
+//                    winner refinement and per-tile SSE / counter partials.
+//  k_assign_direct64 every pair by the FP64 direct formula (the plain FP64
+//                    baseline and the dense-fallback path when the threshold
+//                    makes every pair fail the test).
+//  k_reduce_parts    fixed-order sums of the per-tile partials.
+//  k_quantize        element-wise conversion (tests of the rounding).
+//
+// All kernels take an array of problem descriptors and a prefix array of
+// workgroup counts, so one launch can serve many independent problems; a
+// problem's arithmetic never depends on the other problems in the launch.
+#include "km_device.hpp"
+#include "km_internal.hpp"
+
+namespace km {
+
+// Problem index of workgroup b: largest p with wg_start[p] <= b.
+__device__ inline int find_problem(const int32_t* __restrict__ wg_start, int nprob, int b) {
+  int lo = 0, hi = nprob - 1;
+  while (lo < hi) {
+    int mid = (lo + hi + 1) >> 1;
+    if (wg_start[mid] <= b) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+__device__ inline void raise_status(int* status, int bits) {
+  // one atomic per wave that saw a problem
+  unsigned long long m = __ballot(bits != 0);
+  if (m) {
+    int all = bits;
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) all |= __shfl_xor(all, o, kWave);
+    if ((threadIdx.x & 63) == (int)(__ffsll((long long)m) - 1)) atomicOr(status, all);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Centre preparation.  One thread per (padded) centre row.
+//   Cq[j, 0:DP]  = RNE_low(C[j, 0:d]), zero padded
+//   nc_j         = sum_l Cq[j,l]^2 in FP32, index order (norm of the
+//                  quantised centre, as the expanded formula requires)
+//   cinit[j]     = -nc_j / 2          (accumulator start of the cross term)
+//   ca[j]        = alpha * nc_j / 2   (centre part of the reliability test)
+// Padded rows j >= k: cinit = -inf, ca = 0, so they never win and never fail
+// the test.
+// ---------------------------------------------------------------------------
+template <class L>
+__global__ void __launch_bounds__(256)
+k_prep_centroids(const PrepProb* __restrict__ probs, const int32_t* __restrict__ wg_start, int nprob) {
+  const int pi = find_problem(wg_start, nprob, blockIdx.x);
+  const PrepProb& P = probs[pi];
+  const int j = (blockIdx.x - wg_start[pi]) * 256 + threadIdx.x;
+  if (j >= P.k_pad) return;
+  typename L::S* out = reinterpret_cast<typename L::S*>(P.Cq) + (int64_t)j * P.DP;
+  int bad = 0;
+  if (j < P.k) {
+    const float* c = P.C + (int64_t)j * P.d;
+    float s = 0.0f;
+    for (int l = 0; l < P.d; ++l) {
+      float v = c[l];
+      if (!__builtin_isfinite(v)) bad |= kStatusNonFinite;
+      if (L::kHasRange && __builtin_fabsf(v) >= L::kOverflow) bad |= kStatusRange;
+      typename L::S q = L::cvt(v);
+      out[l] = q;
+      float f = L::tof(q);
+      s = __builtin_fmaf(f, f, s);
+    }
+    for (int l = P.d; l < P.DP; ++l) out[l] = L::cvt(0.0f);
+    float hc = 0.5f * s;
+    P.cinit[j] = -hc;
+    P.ca[j] = P.alpha * hc;
+  } else {
+    for (int l = 0; l < P.DP; ++l) out[l] = L::cvt(0.0f);
+    P.cinit[j] = -__builtin_inff();
+    P.ca[j] = 0.0f;
+  }
+  raise_status(P.status, bad);
+}
+
+// ---------------------------------------------------------------------------
+// Fused mixed-precision assignment.
+//
+// Per pair (x~ = RNE(x), c~ = RNE(c)) the accumulator holds
+//     W = -nc/2 + x~^T c~                      (FP32 accumulation)
+// so that the expanded distance is d^ = nx + nc - 2 x~^T c~ = nx - 2W and the
+// reliability test  d^ > alpha (nx + nc)  (keep) reads
+//     W + alpha nc/2 < (1 - alpha) nx / 2,
+// i.e. a pair is corrected iff  W + ca_j >= hx_i.  The kept pair with the
+// largest W has the smallest d^.  Corrected pairs are recomputed in FP64 by
+// the direct formula from the FP32 data and rounded once to FP32.
+//
+// MODE 0: argmin + refinement + partials.  MODE 1: write every pair's value
+// and flag (materialised distances for reports and tests).
+// ---------------------------------------------------------------------------
+template <class L, int DP, int NB>
+struct AssignCfg {
+  static constexpr int kWaves = 4;
+  static constexpr int kPts = kWaves * NB * 32;           // points per workgroup
+  static constexpr int kLd = DP + (L::KS == 2 ? 4 : 8);   // LDS row stride (elements)
+  static constexpr int kCt = 64;                          // centres per LDS tile
+  static constexpr int kSteps = DP / L::KS;
+  static constexpr int kBytes = 2 * kCt * kLd * (int)sizeof(typename L::S);
+  // 16-byte chunks of one centre tile in global memory
+  static constexpr int kChunks = kCt * DP * (int)sizeof(typename L::S) / 16;
+  static constexpr int kChunksPerThread = (kChunks + 255) / 256;
+  static constexpr int kElemsPerChunk = 16 / (int)sizeof(typename L::S);
+};
+
+template <class L, int DP, int NB, int MODE, bool FALLBACK>
+__global__ void __launch_bounds__(256, 2)
+k_assign_mfma(const AssignProb* __restrict__ probs, const int32_t* __restrict__ wg_start, int nprob) {
+  using Cfg = AssignCfg<L, DP, NB>;
+  using S = typename L::S;
+  constexpr int LD = Cfg::kLd;
+  constexpr int CT = Cfg::kCt;
+
+  __shared__ __attribute__((aligned(16))) unsigned char smem[Cfg::kBytes];
+  __shared__ float s_cinit[2][CT];
+  __shared__ float s_ca[2][CT];
+  __shared__ double s_sse[Cfg::kWaves];
+  __shared__ unsigned long long s_corr[Cfg::kWaves];
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int pi = find_problem(wg_start, nprob, blockIdx.x);
+  const AssignProb& P = probs[pi];
+  const int tile = blockIdx.x - wg_start[pi];
+  const int64_t p0 = (int64_t)tile * Cfg::kPts;
+  const int64_t n = P.n;
+  const int d = P.d;
+  const int nvalid = (int)((n - p0) < Cfg::kPts ? (n - p0) : Cfg::kPts);
+
+  // ---- prologue: each lane loads its matrix-core fragments of the FP32
+  // points straight from HBM, rounds them (RNE) to the low format and forms
+  // the squared norm of the quantised point (FP32; each lane half sums its
+  // own K elements in order, the two halves are then added).
+  typename L::frag bfr[NB][Cfg::kSteps];
+  float nx[NB], hx[NB];
+  const int pw = wave * NB * 32;  // first point of this wave within the tile
+  int bad = 0;
+  const bool vec4 = ((d & 3) == 0) && ((((uintptr_t)P.X) & 15) == 0);
+#pragma unroll
+  for (int cb = 0; cb < NB; ++cb) {
+    const int pl = pw + cb * 32 + (lane & 31);
+    const bool pv = pl < nvalid;
+    const float* xr = P.X + (p0 + (pv ? pl : 0)) * d;
+    float part = 0.0f;
+#pragma unroll
+    for (int s = 0; s < Cfg::kSteps; ++s) {
+      const int o = s * L::KS + (lane >> 5) * L::KV;
+      float v[L::KV];
+      if constexpr (L::KV % 4 == 0) {
+        if (vec4) {
+#pragma unroll
+          for (int u = 0; u < L::KV; u += 4) {
+            float4 q = make_float4(0.f, 0.f, 0.f, 0.f);
+            if (pv && o + u < d) q = *reinterpret_cast<const float4*>(xr + o + u);
+            v[u] = q.x; v[u + 1] = q.y; v[u + 2] = q.z; v[u + 3] = q.w;
+          }
+        } else {
+#pragma unroll
+          for (int u = 0; u < L::KV; ++u) v[u] = (pv && o + u < d) ? xr[o + u] : 0.0f;
+        }
+      } else {
+#pragma unroll
+        for (int u = 0; u < L::KV; ++u) v[u] = (pv && o + u < d) ? xr[o + u] : 0.0f;
+      }
+      typename L::frag f;
+#pragma unroll
+      for (int u = 0; u < L::KV; ++u) {
+        if (!__builtin_isfinite(v[u])) bad |= kStatusNonFinite;
+        if (L::kHasRange && __builtin_fabsf(v[u]) >= L::kOverflow) bad |= kStatusRange;
+        const S q = L::cvt(v[u]);
+        if constexpr (L::KV == 1) f = q; else f[u] = q;
+        const float qf = L::tof(q);
+        part = __builtin_fmaf(qf, qf, part);
+      }
+      bfr[cb][s] = f;
+    }
+    const float other = __shfl_xor(part, 32, kWave);
+    nx[cb] = (lane < 32) ? part + other : other + part;
+    // points past the end never fail the test (no correction reads there)
+    hx[cb] = pv ? 0.5f * (P.oma * nx[cb]) : __builtin_inff();
+  }
+  raise_status(P.status, bad);
+
+  S* const sc0 = reinterpret_cast<S*>(smem);  // two buffers of CT rows
+
+  // running state per column block: best kept (largest W), best corrected
+  float bw[NB];
+  int bj[NB];
+  float cd[NB];
+  int cj[NB];
+#pragma unroll
+  for (int cb = 0; cb < NB; ++cb) {
+    bw[cb] = -__builtin_inff();
+    bj[cb] = -1;
+    cd[cb] = __builtin_inff();
+    cj[cb] = -1;
+  }
+  unsigned long long ncorr = 0;
+
+  const int kpad = P.k_pad;
+  const int ntile = (kpad + CT - 1) / CT;
+  const S* Cq = reinterpret_cast<const S*>(P.Cq);
+
+  // global -> register staging of one centre tile (16-byte chunks)
+  f32x4 stage[Cfg::kChunksPerThread];
+  float st_ci = 0.f, st_ca = 0.f;
+  auto load_tile = [&](int t) {
+    const int rows = (kpad - t * CT) < CT ? (kpad - t * CT) : CT;
+    const f32x4* g = reinterpret_cast<const f32x4*>(Cq + (int64_t)t * CT * DP);
+    const int nchunk = rows * DP / Cfg::kElemsPerChunk;
+#pragma unroll
+    for (int u = 0; u < Cfg::kChunksPerThread; ++u) {
+      const int c = tid + u * 256;
+      if (c < nchunk) stage[u] = g[c];
+    }
+    if (tid < rows) {
+      st_ci = P.cinit[t * CT + tid];
+      st_ca = P.ca[t * CT + tid];
+    }
+  };
+  auto store_tile = [&](int t, int buf) {
+    const int rows = (kpad - t * CT) < CT ? (kpad - t * CT) : CT;
+    const int nchunk = rows * DP / Cfg::kElemsPerChunk;
+    constexpr int CPR = DP / Cfg::kElemsPerChunk;  // chunks per row
+#pragma unroll
+    for (int u = 0; u < Cfg::kChunksPerThread; ++u) {
+      const int c = tid + u * 256;
+      if (c < nchunk) {
+        const int row = c / CPR, col = (c % CPR) * Cfg::kElemsPerChunk;
+        *reinterpret_cast<f32x4*>(sc0 + buf * CT * LD + row * LD + col) = stage[u];
+      }
+    }
+    if (tid < rows) {
+      s_cinit[buf][tid] = st_ci;
+      s_ca[buf][tid] = st_ca;
+    }
+  };
+
+  load_tile(0);
+  store_tile(0, 0);
+  __syncthreads();
+
+  for (int t = 0; t < ntile; ++t) {
+    const int buf = t & 1;
+    if (t + 1 < ntile) load_tile(t + 1);
+    const int rows = (kpad - t * CT) < CT ? (kpad - t * CT) : CT;
+    uint32_t fmask[2][NB];
+#pragma unroll
+    for (int bk = 0; bk < 2; ++bk)
+#pragma unroll
+      for (int cb = 0; cb < NB; ++cb) fmask[bk][cb] = 0;
+    for (int bk = 0; bk < rows / 32; ++bk) {
+      const int jb = t * CT + bk * 32;  // first centre of this 32-block
+      f32x16 ci;
+#pragma unroll
+      for (int r = 0; r < 16; ++r) ci[r] = s_cinit[buf][bk * 32 + acc_row(r, lane)];
+      const float* cab = &s_ca[buf][bk * 32];
+      f32x16 acc[NB];
+#pragma unroll
+      for (int cb = 0; cb < NB; ++cb) acc[cb] = ci;
+      const S* arow = sc0 + buf * CT * LD + (bk * 32 + (lane & 31)) * LD + (lane >> 5) * L::KV;
+#pragma unroll
+      for (int s = 0; s < Cfg::kSteps; ++s) {
+        typename L::frag a;
+        if constexpr (L::KV == 1) a = arow[s * L::KS];
+        else a = *reinterpret_cast<const typename L::frag*>(arow + s * L::KS);
+#pragma unroll
+        for (int cb = 0; cb < NB; ++cb) acc[cb] = L::mfma(a, bfr[cb][s], acc[cb]);
+      }
+      // ---- epilogue ----
+#pragma unroll
+      for (int cb = 0; cb < NB; ++cb) {
+        const int pl = pw + cb * 32 + (lane & 31);
+        uint32_t fm = 0;  // flagged accumulator registers of this lane
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+          const float w = acc[cb][r];
+          const bool flag = FALLBACK && (w + cab[acc_row(r, lane)] >= hx[cb]);
+          if (FALLBACK) fm |= (uint32_t)flag << r;
+          if constexpr (MODE == 0) {
+            const bool better = !flag && (w > bw[cb]);
+            bw[cb] = better ? w : bw[cb];
+            bj[cb] = better ? jb + acc_row(r, lane) : bj[cb];
+          } else {
+            const int j = jb + acc_row(r, lane);
+            if (!flag && pl < nvalid && j < P.k) {
+              const int64_t o = (p0 + pl) * (int64_t)P.k + j;
+              P.D[o] = __builtin_fmaxf(nx[cb] - 2.0f * w, 0.0f);
+              if (P.flagged) P.flagged[o] = 0;
+            }
+          }
+        }
+        if (FALLBACK) fmask[bk][cb] = fm;
+      }
+    }
+    // flagged pairs of this tile: FP64 direct formula from the FP32 originals
+    if constexpr (FALLBACK) {
+#pragma unroll
+      for (int bk = 0; bk < 2; ++bk)
+#pragma unroll
+        for (int cb = 0; cb < NB; ++cb) {
+          uint32_t fm = fmask[bk][cb];
+          const int pl = pw + cb * 32 + (lane & 31);
+          if (!fm || pl >= nvalid) continue;
+          const float* xr = P.X + (p0 + pl) * d;
+          do {
+            const int r = __builtin_ctz(fm);
+            fm &= fm - 1;
+            const int j = t * CT + bk * 32 + acc_row(r, lane);
+            if (j >= P.k) continue;
+            const double dd = sqdist64(xr, P.C + (int64_t)j * d, d);
+            const float df = (float)dd;
+            ncorr += 1;
+            if constexpr (MODE == 0) {
+              if (df < cd[cb] || (df == cd[cb] && j < cj[cb])) {
+                cd[cb] = df;
+                cj[cb] = j;
+              }
+            } else {
+              const int64_t o = (p0 + pl) * (int64_t)P.k + j;
+              P.D[o] = df;
+              if (P.flagged) P.flagged[o] = 1;
+            }
+          } while (fm);
+        }
+    }
+    if (t + 1 < ntile) store_tile(t + 1, buf ^ 1);
+    __syncthreads();
+  }
+
+  // ---- merge the two lanes that share a point, choose, refine ------------
+  double sse = 0.0;
+  if constexpr (MODE == 0) {
+#pragma unroll
+    for (int cb = 0; cb < NB; ++cb) {
+      float ow = __shfl_xor(bw[cb], 32, kWave);
+      int oj = __shfl_xor(bj[cb], 32, kWave);
+      if (ow > bw[cb] || (ow == bw[cb] && oj >= 0 && (bj[cb] < 0 || oj < bj[cb]))) {
+        bw[cb] = ow;
+        bj[cb] = oj;
+      }
+      float od = __shfl_xor(cd[cb], 32, kWave);
+      int ojc = __shfl_xor(cj[cb], 32, kWave);
+      if (od < cd[cb] || (od == cd[cb] && ojc >= 0 && (cj[cb] < 0 || ojc < cj[cb]))) {
+        cd[cb] = od;
+        cj[cb] = ojc;
+      }
+    }
+#pragma unroll
+    for (int cb = 0; cb < NB; ++cb) {
+      if ((cb & 1) != (lane >> 5)) continue;  // lane half cb%2 finishes block cb
+      const int pl = pw + cb * 32 + (lane & 31);
+      if (pl >= nvalid) continue;
+      const float dk = bj[cb] >= 0 ? __builtin_fmaxf(nx[cb] - 2.0f * bw[cb], 0.0f) : __builtin_inff();
+      int lab = bj[cb];
+      if (cj[cb] >= 0 && (cd[cb] < dk || (cd[cb] == dk && cj[cb] < lab) || lab < 0)) lab = cj[cb];
+      if (lab < 0 || lab >= P.k) lab = 0;  // only with non-finite data (status raised)
+      const int64_t p = p0 + pl;
+      const double dd = sqdist64(P.X + p * d, P.C + (int64_t)lab * d, d);
+      P.labels[p] = lab;
+      if (P.mindist) P.mindist[p] = (float)dd;
+      sse += dd;
+    }
+  }
+  sse = wave_sum(sse);
+  unsigned long long nc = wave_sum_u64(ncorr);
+  if (lane == 0) {
+    s_sse[wave] = sse;
+    s_corr[wave] = nc;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    double s = 0.0;
+    unsigned long long c = 0;
+#pragma unroll
+    for (int w = 0; w < Cfg::kWaves; ++w) {
+      s += s_sse[w];
+      c += s_corr[w];
+    }
+    P.sse_part[tile] = s;
+    P.corr_part[tile] = c;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Every pair by the FP64 direct formula.  64 points x 64 centres per step,
+// 256 threads each owning a 4 x 4 block of pairs; FP32 tiles in LDS.
+// CMP64: compare the FP64 values (plain FP64 kernel); otherwise compare the
+// values rounded to FP32 (mixed path with every pair corrected).
+// ---------------------------------------------------------------------------
+template <bool CMP64, int MODE>
+__global__ void __launch_bounds__(256)
+k_assign_direct64(const AssignProb* __restrict__ probs, const int32_t* __restrict__ wg_start, int nprob) {
+  constexpr int TP = 64, TC = 64, DC = 32;  // points, centres, coordinates per chunk
+  __shared__ float sxs[TP][DC + 1];
+  __shared__ float scs[TC][DC + 1];
+  __shared__ double s_best[16][TP];
+  __shared__ int s_bidx[16][TP];
+  __shared__ double s_sse[4];
+  __shared__ unsigned long long s_corr[4];
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int pi = find_problem(wg_start, nprob, blockIdx.x);
+  const AssignProb& P = probs[pi];
+  const int tile = blockIdx.x - wg_start[pi];
+  const int64_t p0 = (int64_t)tile * TP;
+  const int d = P.d, k = P.k;
+  const int nvalid = (int)((P.n - p0) < TP ? (P.n - p0) : TP);
+  const int pg = tid & 15, cg = tid >> 4;  // points pg*4.., centres cg*4..
+
+  int bad = 0;
+  double best[4];
+  int bidx[4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a) {
+    best[a] = __builtin_inf();
+    bidx[a] = -1;
+  }
+  for (int c0 = 0; c0 < k; c0 += TC) {
+    double acc[4][4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int b = 0; b < 4; ++b) acc[a][b] = 0.0;
+    for (int l0 = 0; l0 < d; l0 += DC) {
+      __syncthreads();
+      for (int e = tid; e < TP * DC; e += 256) {
+        const int p = e / DC, l = e % DC;
+        float v = 0.f;
+        if (p < nvalid && l0 + l < d) {
+          v = P.X[(p0 + p) * d + l0 + l];
+          if (c0 == 0) {
+            if (!__builtin_isfinite(v)) bad |= kStatusNonFinite;
+          }
+        }
+        sxs[p][l] = v;
+        float w = 0.f;
+        if (c0 + p < k && l0 + l < d) w = P.C[(int64_t)(c0 + p) * d + l0 + l];
+        scs[p][l] = w;
+      }
+      __syncthreads();
+      const int lmax = (d - l0) < DC ? (d - l0) : DC;
+      for (int l = 0; l < lmax; ++l) {
+        double xv[4], cv[4];
+#pragma unroll
+        for (int a = 0; a < 4; ++a) xv[a] = (double)sxs[pg * 4 + a][l];
+#pragma unroll
+        for (int b = 0; b < 4; ++b) cv[b] = (double)scs[cg * 4 + b][l];
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+          for (int b = 0; b < 4; ++b) {
+            const double e = xv[a] - cv[b];
+            acc[a][b] = __builtin_fma(e, e, acc[a][b]);
+          }
+      }
+    }
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int b = 0; b < 4; ++b) {
+        const int j = c0 + cg * 4 + b;
+        const int p = pg * 4 + a;
+        if (j < k && p < nvalid) {
+          if constexpr (MODE == 0) {
+            const double v = CMP64 ? acc[a][b] : (double)(float)acc[a][b];
+            if (v < best[a]) {  // centres visited in increasing order
+              best[a] = v;
+              bidx[a] = j;
+            }
+          } else {
+            const int64_t o = (p0 + p) * (int64_t)k + j;
+            P.D[o] = (float)acc[a][b];
+            if (P.flagged) P.flagged[o] = 1;
+          }
+        }
+      }
+  }
+  raise_status(P.status, bad);
+  double sse = 0.0;
+  unsigned long long nc = 0;
+  if constexpr (MODE == 0) {
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+      s_best[cg][pg * 4 + a] = best[a];
+      s_bidx[cg][pg * 4 + a] = bidx[a];
+    }
+    __syncthreads();
+    if (tid < TP && tid < nvalid) {
+      double bv = __builtin_inf();
+      int bi = -1;
+      for (int g = 0; g < 16; ++g) {
+        const double v = s_best[g][tid];
+        const int i = s_bidx[g][tid];
+        if (i >= 0 && (v < bv || (v == bv && i < bi))) {
+          bv = v;
+          bi = i;
+        }
+      }
+      const int64_t p = p0 + tid;
+      if (bi < 0) bi = 0;  // only with non-finite data (status raised)
+      const double dd = sqdist64(P.X + p * d, P.C + (int64_t)bi * d, d);
+      P.labels[p] = bi;
+      if (P.mindist) P.mindist[p] = (float)dd;
+      sse = dd;
+    }
+  }
+  if (!CMP64 && tid < TP && tid < nvalid) nc = (unsigned long long)k;
+  sse = wave_sum(sse);
+  nc = wave_sum_u64(nc);
+  if (lane == 0) {
+    s_sse[wave] = sse;
+    s_corr[wave] = nc;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    P.sse_part[tile] = s_sse[0] + s_sse[1] + s_sse[2] + s_sse[3];
+    P.corr_part[tile] = s_corr[0] + s_corr[1] + s_corr[2] + s_corr[3];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Per-problem fixed-order sums of the per-tile partials.  One workgroup per
+// problem.  Writes the SSE to the caller's scalar (if any) and the problem's
+// result record (SSE, corrected pairs, status).
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256)
+k_reduce_parts(const ReduceProb* __restrict__ probs) {
+  const ReduceProb& P = probs[blockIdx.x];
+  __shared__ double ss[256];
+  __shared__ unsigned long long sc[256];
+  const int tid = threadIdx.x;
+  double s = 0.0;
+  unsigned long long c = 0;
+  for (int i = tid; i < P.nparts; i += 256) {
+    s += P.sse_part[i];
+    c += P.corr_part[i];
+  }
+  ss[tid] = s;
+  sc[tid] = c;
+  __syncthreads();
+  for (int o = 128; o >= 1; o >>= 1) {
+    if (tid < o) {
+      ss[tid] += ss[tid + o];
+      sc[tid] += sc[tid + o];
+    }
+    __syncthreads();
+  }
+  if (tid == 0) {
+    if (P.sse_out) *P.sse_out = ss[0];
+    if (P.result) {
+      P.result->sse = ss[0];
+      P.result->n_corrected += (long long)sc[0];
+      P.result->n_pairs += P.pairs;
+      P.result->status |= *P.status;
+    }
+  }
+}
+
+template <class L>
+__global__ void k_quantize(const float* __restrict__ in, int64_t count, uint16_t* __restrict__ out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < count) out[i] = L::bits(L::cvt(in[i]));
+}
+
+// ---------------------------------------------------------------------------
+// Host-side launchers
+// ---------------------------------------------------------------------------
+template <class L>
+static hipError_t launch_prep_t(const PrepProb* dprobs, const int32_t* dstart, int nprob, int nwg,
+                                hipStream_t st) {
+  hipLaunchKernelGGL(k_prep_centroids<L>, dim3(nwg), dim3(256), 0, st, dprobs, dstart, nprob);
+  return hipGetLastError();
+}
+
+hipError_t launch_prep(int low, const PrepProb* dprobs, const int32_t* dstart, int nprob, int nwg,
+                       hipStream_t st) {
+  switch (low) {
+    case kLowFP16: return launch_prep_t<LowF16>(dprobs, dstart, nprob, nwg, st);
+    case kLowBF16: return launch_prep_t<LowBF16>(dprobs, dstart, nprob, nwg, st);
+    case kLowFP32: return launch_prep_t<LowF32>(dprobs, dstart, nprob, nwg, st);
+  }
+  return hipErrorInvalidValue;
+}
+
+template <class L, int DP, int NB>
+static hipError_t launch_mfma_t(int mode, bool fallback, const AssignProb* dprobs, const int32_t* dstart,
+                                int nprob, int nwg, hipStream_t st) {
+  if (mode == 0) {
+    if (fallback)
+      hipLaunchKernelGGL((k_assign_mfma<L, DP, NB, 0, true>), dim3(nwg), dim3(256), 0, st, dprobs, dstart, nprob);
+    else
+      hipLaunchKernelGGL((k_assign_mfma<L, DP, NB, 0, false>), dim3(nwg), dim3(256), 0, st, dprobs, dstart, nprob);
+  } else {
+    if (fallback)
+      hipLaunchKernelGGL((k_assign_mfma<L, DP, NB, 1, true>), dim3(nwg), dim3(256), 0, st, dprobs, dstart, nprob);
+    else
+      hipLaunchKernelGGL((k_assign_mfma<L, DP, NB, 1, false>), dim3(nwg), dim3(256), 0, st, dprobs, dstart, nprob);
+  }
+  return hipGetLastError();
+}
+
+template <class L>
+static hipError_t launch_mfma_l(int DP, int mode, bool fallback, const AssignProb* dprobs,
+                                const int32_t* dstart, int nprob, int nwg, hipStream_t st) {
+  switch (DP) {
+    case 16: return launch_mfma_t<L, 16, mfma_nb(kLowFP16, 16)>(mode, fallback, dprobs, dstart, nprob, nwg, st);
+    case 32: return launch_mfma_t<L, 32, mfma_nb(kLowFP16, 32)>(mode, fallback, dprobs, dstart, nprob, nwg, st);
+    case 64: return launch_mfma_t<L, 64, mfma_nb(kLowFP16, 64)>(mode, fallback, dprobs, dstart, nprob, nwg, st);
+    case 128: return launch_mfma_t<L, 128, mfma_nb(kLowFP16, 128)>(mode, fallback, dprobs, dstart, nprob, nwg, st);
+    case 256: return launch_mfma_t<L, 256, mfma_nb(kLowFP16, 256)>(mode, fallback, dprobs, dstart, nprob, nwg, st);
+  }
+  return hipErrorInvalidValue;
+}
+
+template <>
+hipError_t launch_mfma_l<LowF32>(int DP, int mode, bool fallback, const AssignProb* dprobs,
+                                 const int32_t* dstart, int nprob, int nwg, hipStream_t st) {
+  switch (DP) {
+    case 16: return launch_mfma_t<LowF32, 16, mfma_nb(kLowFP32, 16)>(mode, fallback, dprobs, dstart, nprob, nwg, st);
+    case 32: return launch_mfma_t<LowF32, 32, mfma_nb(kLowFP32, 32)>(mode, fallback, dprobs, dstart, nprob, nwg, st);
+    case 64: return launch_mfma_t<LowF32, 64, mfma_nb(kLowFP32, 64)>(mode, fallback, dprobs, dstart, nprob, nwg, st);
+    case 128: return launch_mfma_t<LowF32, 128, mfma_nb(kLowFP32, 128)>(mode, fallback, dprobs, dstart, nprob, nwg, st);
+  }
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_assign_mfma(int low, int DP, int mode, bool fallback, const AssignProb* dprobs,
+                              const int32_t* dstart, int nprob, int nwg, hipStream_t st) {
+  switch (low) {
+    case kLowFP16: return launch_mfma_l<LowF16>(DP, mode, fallback, dprobs, dstart, nprob, nwg, st);
+    case kLowBF16: return launch_mfma_l<LowBF16>(DP, mode, fallback, dprobs, dstart, nprob, nwg, st);
+    case kLowFP32: return launch_mfma_l<LowF32>(DP, mode, fallback, dprobs, dstart, nprob, nwg, st);
+  }
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_assign_direct64(bool cmp64, int mode, const AssignProb* dprobs, const int32_t* dstart,
+                                  int nprob, int nwg, hipStream_t st) {
+  if (mode == 0) {
+    if (cmp64) hipLaunchKernelGGL((k_assign_direct64<true, 0>), dim3(nwg), dim3(256), 0, st, dprobs, dstart, nprob);
+    else hipLaunchKernelGGL((k_assign_direct64<false, 0>), dim3(nwg), dim3(256), 0, st, dprobs, dstart, nprob);
+  } else {
+    hipLaunchKernelGGL((k_assign_direct64<true, 1>), dim3(nwg), dim3(256), 0, st, dprobs, dstart, nprob);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_reduce_parts(const ReduceProb* dprobs, int nprob, hipStream_t st) {
+  hipLaunchKernelGGL(k_reduce_parts, dim3(nprob), dim3(256), 0, st, dprobs);
+  return hipGetLastError();
+}
+
+hipError_t launch_quantize(int low, const float* in, int64_t count, uint16_t* out, hipStream_t st) {
+  const int64_t nwg = (count + 255) / 256;
+  if (nwg == 0) return hipSuccess;
+  if (low == kLowFP16) hipLaunchKernelGGL(k_quantize<LowF16>, dim3((unsigned)nwg), dim3(256), 0, st, in, count, out);
+  else if (low == kLowBF16) hipLaunchKernelGGL(k_quantize<LowBF16>, dim3((unsigned)nwg), dim3(256), 0, st, in, count, out);
+  else return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
+}  // namespace km

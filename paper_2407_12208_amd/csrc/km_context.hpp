@@ -1,0 +1,118 @@
+// km_context.hpp -- host-side library state: the context (device, workspace
+// arena, descriptor uploader) and the planning helpers shared by the C ABI
+// entry points and the server.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <mutex>
+#include <vector>
+
+#include "../../include/kmeans.h"
+#include "km_internal.hpp"
+
+namespace km {
+
+// Device bump allocator, reset per call; grows (after draining the device)
+// when a call needs more than it holds.
+struct Arena {
+  char* base = nullptr;
+  size_t cap = 0;
+  size_t used = 0;
+  static size_t align(size_t x) { return (x + 255) & ~size_t(255); }
+  hipError_t ensure(size_t bytes) {
+    if (bytes <= cap) return hipSuccess;
+    if (base) {
+      hipError_t e = hipDeviceSynchronize();
+      if (e != hipSuccess) return e;
+      (void)hipFree(base);
+      base = nullptr;
+      cap = 0;
+    }
+    size_t c = bytes + bytes / 4 + (1 << 20);
+    hipError_t e = hipMalloc(reinterpret_cast<void**>(&base), c);
+    if (e != hipSuccess) {
+      base = nullptr;
+      return e;
+    }
+    cap = c;
+    return hipSuccess;
+  }
+  void reset() { used = 0; }
+  template <class T>
+  T* take(size_t count) {
+    T* p = reinterpret_cast<T*>(base + used);
+    used += align(count * sizeof(T));
+    return p;
+  }
+};
+
+// Size accumulator used to plan an Arena before carving it.
+struct Plan {
+  size_t bytes = 0;
+  template <class T>
+  void add(size_t count) { bytes += Arena::align(count * sizeof(T)); }
+};
+
+// Pinned host ring + device ring for small descriptor uploads that are
+// ordered on the caller's stream.
+struct Uploader {
+  char* host = nullptr;
+  char* dev = nullptr;
+  size_t cap = 0;
+  size_t head = 0;
+  hipError_t init(size_t bytes);
+  void destroy();
+  // Copies `bytes` from src into the ring and enqueues the H2D copy on st;
+  // returns the device address (nullptr on failure).
+  void* put(const void* src, size_t bytes, hipStream_t st);
+};
+
+struct km_context_impl {
+  int device = 0;
+  int num_cu = 0;
+  Arena arena;
+  Uploader up;
+  double* h_scalar = nullptr;     // pinned: shift read-back
+  KResult* h_result = nullptr;    // pinned: result read-back (up to kMaxResults)
+  static constexpr int kMaxResults = 4096;
+};
+
+// Threshold alpha for (prec, d): -1 = no fallback, +inf = always correct.
+double alpha_for(const km_precision& p, int d);
+km_precision precision_or_default(const km_precision* p);
+int32_t validate_precision(const km_precision& p);
+int32_t status_from_bits(int bits);
+
+// How a problem's assignment pass is executed.
+enum class Route { Mfma, MfmaNoFallback, Direct64Exact, Direct64All };
+struct AssignPlan {
+  Route route;
+  int low;
+  int DP;
+  int k_pad;
+  int nwg;          // workgroups of the assignment kernel
+  float alpha_f;    // alpha as applied (FP32)
+  float oma;        // 1 - alpha (FP32)
+  double alpha_used;
+};
+AssignPlan plan_assign(const km_precision& p, int64_t n, int d, int k);
+size_t cq_elem_bytes(int low);
+
+// Launch helpers working on arrays of problems that share one AssignPlan
+// shape (same route, low format and DP).
+hipError_t run_prep(km_context_impl* ctx, int low, const std::vector<PrepProb>& probs,
+                    const std::vector<int>& kpads, hipStream_t st);
+hipError_t run_assign(km_context_impl* ctx, const AssignPlan& shape, int mode,
+                      const std::vector<AssignProb>& probs, const std::vector<int>& nwgs, hipStream_t st);
+hipError_t run_reduce(km_context_impl* ctx, const std::vector<ReduceProb>& probs, hipStream_t st);
+hipError_t run_update(km_context_impl* ctx, const std::vector<UpdateProb>& probs, hipStream_t st);
+
+// Workspace sizes of one problem's centre update.
+void plan_update(Plan& pl, int64_t n, int d, int k);
+UpdateProb carve_update(Arena& a, int64_t n, int d, int k);
+
+}  // namespace km
+
+struct km_context : km::km_context_impl {};

@@ -1,0 +1,122 @@
+// km_device.hpp -- device-side building blocks shared by the gfx950 kernels:
+// low-precision formats with their matrix-core instructions, the FP64 direct
+// squared distance, and wavefront helpers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace km {
+
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
+constexpr int kWave = 64;
+
+
+// ---------------------------------------------------------------------------
+// Low-precision formats.  Each provides: the storage type S; the matrix-core
+// fragment of one lane for a 32x32 output block (KV consecutive K elements),
+// the K extent KS of one instruction, the round-to-nearest-even conversion
+// from FP32, the overflow threshold (inputs at or above it round to inf),
+// and the 32x32 MFMA D = A*B + C with FP32 accumulation.
+//
+// Operand layout of the 32x32xKS instructions (lane l = 0..63):
+//   A: row (l % 32), K elements [(l/32)*KV, (l/32)*KV + KV)
+//   B: column (l % 32), same K elements
+//   D: column (l % 32), rows 8*(r/4) + 4*(l/32) + (r%4) for r = 0..15
+// ---------------------------------------------------------------------------
+struct LowF16 {
+  using S = _Float16;
+  using frag = f16x8;
+  static constexpr int KS = 16, KV = 8;
+  static constexpr bool kHasRange = true;
+  // binary16: the largest finite value is 65504; halfway to 2^16 is 65520.
+  static constexpr float kOverflow = 65520.0f;
+  __device__ static inline S cvt(float x) { return (S)x; }
+  __device__ static inline float tof(S v) { return (float)v; }
+  __device__ static inline uint16_t bits(S v) { return __builtin_bit_cast(uint16_t, v); }
+  __device__ static inline f32x16 mfma(frag a, frag b, f32x16 c) {
+    return __builtin_amdgcn_mfma_f32_32x32x16_f16(a, b, c, 0, 0, 0);
+  }
+};
+
+struct LowBF16 {
+  using S = __bf16;
+  using frag = bf16x8;
+  static constexpr int KS = 16, KV = 8;
+  static constexpr bool kHasRange = false;  // same exponent range as FP32
+  static constexpr float kOverflow = 0.0f;
+  __device__ static inline S cvt(float x) { return (S)x; }
+  __device__ static inline float tof(S v) { return (float)v; }
+  __device__ static inline uint16_t bits(S v) { return __builtin_bit_cast(uint16_t, v); }
+  __device__ static inline f32x16 mfma(frag a, frag b, f32x16 c) {
+    return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0);
+  }
+};
+
+struct LowF32 {
+  using S = float;
+  using frag = float;
+  static constexpr int KS = 2, KV = 1;
+  static constexpr bool kHasRange = false;
+  static constexpr float kOverflow = 0.0f;
+  __device__ static inline S cvt(float x) { return x; }
+  __device__ static inline float tof(S v) { return v; }
+  __device__ static inline uint16_t bits(S) { return 0; }
+  __device__ static inline f32x16 mfma(frag a, frag b, f32x16 c) {
+    return __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, c, 0, 0, 0);
+  }
+};
+
+// Row of the 32x32 output block held in accumulator register r by lane l.
+__device__ __host__ constexpr int acc_row(int r, int lane) {
+  return 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+}
+
+// ---------------------------------------------------------------------------
+// Direct formula eq:dist-direct in FP64 from FP32 data: differences and the
+// running sum in FP64, coordinates in index order (fused multiply-add).
+// ---------------------------------------------------------------------------
+__device__ inline double sqdist64(const float* __restrict__ x,
+                                  const float* __restrict__ c, int d) {
+  double s = 0.0;
+  int l = 0;
+  if ((((uintptr_t)x | (uintptr_t)c) & 15) == 0 && (d & 3) == 0) {
+    for (; l < d; l += 4) {
+      float4 a = *reinterpret_cast<const float4*>(x + l);
+      float4 b = *reinterpret_cast<const float4*>(c + l);
+      double e0 = (double)a.x - (double)b.x;
+      double e1 = (double)a.y - (double)b.y;
+      double e2 = (double)a.z - (double)b.z;
+      double e3 = (double)a.w - (double)b.w;
+      s = __builtin_fma(e0, e0, s);
+      s = __builtin_fma(e1, e1, s);
+      s = __builtin_fma(e2, e2, s);
+      s = __builtin_fma(e3, e3, s);
+    }
+  } else {
+    for (; l < d; ++l) {
+      double e = (double)x[l] - (double)c[l];
+      s = __builtin_fma(e, e, s);
+    }
+  }
+  return s;
+}
+
+// Wavefront sum of a double in a fixed butterfly order (deterministic).
+__device__ inline double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, kWave);
+  return v;
+}
+
+__device__ inline unsigned long long wave_sum_u64(unsigned long long v) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, kWave);
+  return v;
+}
+
+}  // namespace km

@@ -1,0 +1,121 @@
+// km_internal.hpp -- structures shared by the host-side library code and the
+// kernels (problem descriptors passed to the device) and the launcher
+// declarations.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace km {
+
+constexpr int kLowFP16 = 0;
+constexpr int kLowBF16 = 1;
+constexpr int kLowFP32 = 2;
+constexpr int kExact64 = 3;
+
+// Status bits raised by the kernels (a single int per problem).
+constexpr int kStatusNonFinite = 1;
+constexpr int kStatusRange = 2;
+constexpr int kStatusBadLabel = 4;
+
+// Padded coordinate extent of the matrix-core kernels (multiple of the K
+// extent of one instruction; 16 for every format so layouts agree).
+constexpr int padded_dim(int d) {
+  return d <= 16 ? 16 : d <= 32 ? 32 : d <= 64 ? 64 : d <= 128 ? 128 : d <= 256 ? 256 : -1;
+}
+
+// 32-point column blocks per wave (the point fragments of all of them stay in
+// registers for the whole sweep over the centres).
+constexpr int mfma_nb(int low, int DP) {
+  return low == kLowFP32 ? (DP <= 32 ? 2 : 1)
+                         : (DP <= 32 ? 4 : DP <= 128 ? 2 : 1);
+}
+constexpr int mfma_points_per_wg(int low, int DP) { return 4 * 32 * mfma_nb(low, DP); }
+constexpr int kDirectPointsPerWg = 64;
+
+// Accumulated per-problem results on the device.
+struct KResult {
+  double sse;               // SSE of the last assignment pass
+  long long n_corrected;    // summed over passes
+  long long n_pairs;        // summed over passes
+  int status;               // OR of the status bits seen
+  int pad;
+  double shift;             // max centre move of the last update
+};
+
+struct PrepProb {
+  const float* C;  // k x d FP32
+  void* Cq;        // k_pad x DP low precision (output)
+  float* cinit;    // k_pad (output)
+  float* ca;       // k_pad (output)
+  int* status;
+  float alpha;
+  int k, k_pad, d, DP;
+};
+
+struct AssignProb {
+  const float* X;       // n x d
+  const float* C;       // k x d (FP32 originals, for the FP64 direct formula)
+  const void* Cq;       // k_pad x DP quantised centres
+  const float* cinit;   // k_pad
+  const float* ca;      // k_pad
+  int32_t* labels;      // n
+  float* mindist;       // n, nullable
+  float* D;             // pairwise mode: n x k
+  uint8_t* flagged;     // pairwise mode: n x k, nullable
+  double* sse_part;     // one per workgroup of this problem
+  unsigned long long* corr_part;
+  int* status;
+  int64_t n;
+  int d, k, k_pad;
+  float oma;            // 1 - alpha (FP32)
+};
+
+struct ReduceProb {
+  const double* sse_part;
+  const unsigned long long* corr_part;
+  const int* status;
+  double* sse_out;      // nullable (caller's scalar)
+  KResult* result;      // nullable
+  long long pairs;
+  int nparts;
+};
+
+// Centre update, one problem.
+struct UpdateProb {
+  const float* X;
+  const int32_t* labels;
+  const float* C_old;
+  float* C_new;
+  long long* counts_out;   // k, nullable
+  double* shift_out;       // nullable
+  KResult* result;         // nullable
+  // workspace
+  int32_t* hist;           // k * ntiles (cluster-major)
+  int32_t* offs;           // k * ntiles
+  int32_t* perm;           // n
+  int32_t* cstart;         // k+1 cluster starts in perm
+  int32_t* chunk_start;    // k+1 chunk starts
+  double* chunk_sum;       // (n/256 + k) * d
+  double* shift2;          // k
+  int* status;
+  int64_t n;
+  int d, k, ntiles;
+};
+
+hipError_t launch_prep(int low, const PrepProb* dprobs, const int32_t* dstart, int nprob, int nwg,
+                       hipStream_t st);
+hipError_t launch_assign_mfma(int low, int DP, int mode, bool fallback, const AssignProb* dprobs,
+                              const int32_t* dstart, int nprob, int nwg, hipStream_t st);
+hipError_t launch_assign_direct64(bool cmp64, int mode, const AssignProb* dprobs, const int32_t* dstart,
+                                  int nprob, int nwg, hipStream_t st);
+hipError_t launch_reduce_parts(const ReduceProb* dprobs, int nprob, hipStream_t st);
+hipError_t launch_quantize(int low, const float* in, int64_t count, uint16_t* out, hipStream_t st);
+
+// centre update (km_update.hip)
+constexpr int kUpdTile = 1024;   // points per histogram / scatter tile
+constexpr int kUpdChunk = 256;   // members per partial sum
+hipError_t launch_update(const UpdateProb* dprobs, const UpdateProb* hprobs, int nprob,
+                         const int32_t* dscratch_i32, hipStream_t st);
+
+}  // namespace km

@@ -1,0 +1,269 @@
+// km_update.hip -- centre update of Lloyd's iteration (eq:center,
+// Algorithm alg:mp-kmeans) on gfx950.
+//
+// c_j <- fl32( (sum_{i: label_i = j} x_i) / m_j ),  m_j = 0 keeps c_j.
+//
+// The sums are FP64 and their order is fixed by the data alone (never by the
+// launch or by other problems sharing it), so results are bitwise
+// reproducible and identical whether a problem runs alone or batched:
+//   1. hist      per 1024-point tile, label counts (integer LDS atomics:
+//                order-free);
+//   2. scan_rel  per cluster, exclusive scan of its tile counts;
+//   3. scan_cl   per problem, cluster starts and chunk starts;
+//   4. scatter   stable counting sort of point indices by label: members of
+//                a cluster appear in ascending point order;
+//   5. chunksum  one wave per chunk of <= 256 consecutive members of one
+//                cluster, lanes over coordinates, sequential FP64 sums;
+//   6. finalize  per cluster, sum of its chunk partials in order, division,
+//                one rounding to FP32, empty clusters keep their centre,
+//                squared move;
+//   7. shift     per problem, max_j ||c_j^new - c_j^old|| (FP64).
+// No floating-point atomics anywhere.
+#include "km_device.hpp"
+#include "km_internal.hpp"
+
+namespace km {
+
+__device__ inline int find_prob(const int32_t* __restrict__ start, int nprob, int b) {
+  int lo = 0, hi = nprob - 1;
+  while (lo < hi) {
+    int mid = (lo + hi + 1) >> 1;
+    if (start[mid] <= b) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+constexpr int kHistSlice = 8192;  // clusters counted per LDS pass
+
+// 1. per-tile label histogram -> hist[j * ntiles + tile]
+__global__ void __launch_bounds__(256)
+k_upd_hist(const UpdateProb* __restrict__ probs, const int32_t* __restrict__ wg_start, int nprob) {
+  __shared__ int cnt[kHistSlice];
+  const int pi = find_prob(wg_start, nprob, blockIdx.x);
+  const UpdateProb& P = probs[pi];
+  const int tile = blockIdx.x - wg_start[pi];
+  const int64_t p0 = (int64_t)tile * kUpdTile;
+  const int m = (int)((P.n - p0) < kUpdTile ? (P.n - p0) : kUpdTile);
+  int bad = 0;
+  for (int s0 = 0; s0 < P.k; s0 += kHistSlice) {
+    const int sl = (P.k - s0) < kHistSlice ? (P.k - s0) : kHistSlice;
+    for (int j = threadIdx.x; j < sl; j += 256) cnt[j] = 0;
+    __syncthreads();
+    for (int i = threadIdx.x; i < m; i += 256) {
+      const int lab = P.labels[p0 + i];
+      if (lab < 0 || lab >= P.k) bad = 1;
+      else if (lab >= s0 && lab < s0 + sl) atomicAdd(&cnt[lab - s0], 1);
+    }
+    __syncthreads();
+    for (int j = threadIdx.x; j < sl; j += 256) P.hist[(int64_t)(s0 + j) * P.ntiles + tile] = cnt[j];
+    __syncthreads();
+  }
+  if (bad) atomicOr(P.status, kStatusBadLabel);
+}
+
+// 2. per cluster: exclusive scan over its tiles -> offs, total -> cstart[j]
+__global__ void __launch_bounds__(256)
+k_upd_scan_rel(const UpdateProb* __restrict__ probs, const int32_t* __restrict__ wg_start, int nprob) {
+  __shared__ int part[256];
+  const int pi = find_prob(wg_start, nprob, blockIdx.x);
+  const UpdateProb& P = probs[pi];
+  const int j = blockIdx.x - wg_start[pi];
+  const int T = P.ntiles;
+  const int per = (T + 255) / 256;
+  const int t0 = threadIdx.x * per;
+  const int32_t* h = P.hist + (int64_t)j * T;
+  int32_t* o = P.offs + (int64_t)j * T;
+  int s = 0;
+  for (int t = t0; t < t0 + per && t < T; ++t) s += h[t];
+  part[threadIdx.x] = s;
+  __syncthreads();
+  // Hillis-Steele inclusive scan of the 256 partial sums
+  for (int off = 1; off < 256; off <<= 1) {
+    int v = threadIdx.x >= off ? part[threadIdx.x - off] : 0;
+    __syncthreads();
+    part[threadIdx.x] += v;
+    __syncthreads();
+  }
+  int run = threadIdx.x > 0 ? part[threadIdx.x - 1] : 0;
+  for (int t = t0; t < t0 + per && t < T; ++t) {
+    o[t] = run;
+    run += h[t];
+  }
+  if (threadIdx.x == 255) P.cstart[j] = part[255];  // count, scanned by k_upd_scan_cl
+}
+
+// 3. per problem: counts -> exclusive cluster starts and chunk starts
+__global__ void __launch_bounds__(1024)
+k_upd_scan_cl(const UpdateProb* __restrict__ probs) {
+  __shared__ int a[1024];
+  __shared__ int b[1024];
+  __shared__ int carry[2];
+  const UpdateProb& P = probs[blockIdx.x];
+  const int tid = threadIdx.x;
+  if (tid == 0) {
+    carry[0] = 0;
+    carry[1] = 0;
+  }
+  __syncthreads();
+  for (int base = 0; base < P.k; base += 1024) {
+    const int j = base + tid;
+    const int mj = j < P.k ? P.cstart[j] : 0;
+    const int cj = (mj + kUpdChunk - 1) / kUpdChunk;
+    a[tid] = mj;
+    b[tid] = cj;
+    __syncthreads();
+    for (int off = 1; off < 1024; off <<= 1) {
+      int va = tid >= off ? a[tid - off] : 0;
+      int vb = tid >= off ? b[tid - off] : 0;
+      __syncthreads();
+      a[tid] += va;
+      b[tid] += vb;
+      __syncthreads();
+    }
+    const int c0 = carry[0], c1 = carry[1];
+    if (j < P.k) {
+      P.cstart[j] = c0 + a[tid] - mj;
+      P.chunk_start[j] = c1 + b[tid] - cj;
+    }
+    __syncthreads();
+    if (tid == 1023) {
+      carry[0] = c0 + a[1023];
+      carry[1] = c1 + b[1023];
+    }
+    __syncthreads();
+  }
+  if (tid == 0) {
+    P.cstart[P.k] = carry[0];
+    P.chunk_start[P.k] = carry[1];
+  }
+}
+
+// 4. stable scatter of point indices into cluster order
+__global__ void __launch_bounds__(256)
+k_upd_scatter(const UpdateProb* __restrict__ probs, const int32_t* __restrict__ wg_start, int nprob) {
+  __shared__ int lab_s[kUpdTile];
+  const int pi = find_prob(wg_start, nprob, blockIdx.x);
+  const UpdateProb& P = probs[pi];
+  const int tile = blockIdx.x - wg_start[pi];
+  const int64_t p0 = (int64_t)tile * kUpdTile;
+  const int m = (int)((P.n - p0) < kUpdTile ? (P.n - p0) : kUpdTile);
+  for (int i = threadIdx.x; i < m; i += 256) lab_s[i] = P.labels[p0 + i];
+  __syncthreads();
+  for (int i = threadIdx.x; i < m; i += 256) {
+    const int lab = lab_s[i];
+    if (lab < 0 || lab >= P.k) continue;
+    int rank = 0;
+    for (int q = 0; q < i; ++q) rank += (lab_s[q] == lab);
+    const int pos = P.cstart[lab] + P.offs[(int64_t)lab * P.ntiles + tile] + rank;
+    P.perm[pos] = (int32_t)(p0 + i);
+  }
+}
+
+// 5. one wave per chunk of <= 256 members of a cluster; lanes over coordinates
+__global__ void __launch_bounds__(256)
+k_upd_chunksum(const UpdateProb* __restrict__ probs, const int32_t* __restrict__ wg_start, int nprob) {
+  const int pi = find_prob(wg_start, nprob, blockIdx.x);
+  const UpdateProb& P = probs[pi];
+  const int c = (blockIdx.x - wg_start[pi]) * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (c >= P.chunk_start[P.k]) return;
+  // cluster owning chunk c
+  int lo = 0, hi = P.k - 1;
+  while (lo < hi) {
+    int mid = (lo + hi + 1) >> 1;
+    if (P.chunk_start[mid] <= c) lo = mid; else hi = mid - 1;
+  }
+  const int j = lo;
+  const int m0 = P.cstart[j] + (c - P.chunk_start[j]) * kUpdChunk;
+  const int m1 = (m0 + kUpdChunk) < P.cstart[j + 1] ? (m0 + kUpdChunk) : P.cstart[j + 1];
+  const int d = P.d;
+  for (int l0 = 0; l0 < d; l0 += 64) {
+    const int l = l0 + lane;
+    double s = 0.0;
+    if (l < d) {
+      for (int mm = m0; mm < m1; ++mm) s += (double)P.X[(int64_t)P.perm[mm] * d + l];
+      P.chunk_sum[(int64_t)c * d + l] = s;
+    }
+  }
+}
+
+// 6. per cluster: ordered sum of chunk partials, divide, round, keep empty
+__global__ void __launch_bounds__(256)
+k_upd_finalize(const UpdateProb* __restrict__ probs, const int32_t* __restrict__ wg_start, int nprob) {
+  const int pi = find_prob(wg_start, nprob, blockIdx.x);
+  const UpdateProb& P = probs[pi];
+  const int j = (blockIdx.x - wg_start[pi]) * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (j >= P.k) return;
+  const int mj = P.cstart[j + 1] - P.cstart[j];
+  const int c0 = P.chunk_start[j], c1 = P.chunk_start[j + 1];
+  const int d = P.d;
+  double mv2 = 0.0;
+  for (int l0 = 0; l0 < d; l0 += 64) {
+    const int l = l0 + lane;
+    if (l < d) {
+      const float old = P.C_old[(int64_t)j * d + l];
+      float nv = old;
+      if (mj > 0) {
+        double s = 0.0;
+        for (int c = c0; c < c1; ++c) s += P.chunk_sum[(int64_t)c * d + l];
+        nv = (float)(s / (double)mj);
+      }
+      P.C_new[(int64_t)j * d + l] = nv;
+      const double df = (double)nv - (double)old;
+      mv2 += df * df;
+    }
+  }
+  mv2 = wave_sum(mv2);
+  if (lane == 0) {
+    P.shift2[j] = mv2;
+    if (P.counts_out) P.counts_out[j] = mj;
+  }
+}
+
+// 7. per problem: shift = max_j sqrt(shift2[j])
+__global__ void __launch_bounds__(256)
+k_upd_shift(const UpdateProb* __restrict__ probs) {
+  __shared__ double mx[256];
+  const UpdateProb& P = probs[blockIdx.x];
+  double v = 0.0;
+  for (int j = threadIdx.x; j < P.k; j += 256) v = __builtin_fmax(v, P.shift2[j]);
+  mx[threadIdx.x] = v;
+  __syncthreads();
+  for (int o = 128; o >= 1; o >>= 1) {
+    if (threadIdx.x < o) mx[threadIdx.x] = __builtin_fmax(mx[threadIdx.x], mx[threadIdx.x + o]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    const double s = __builtin_sqrt(mx[0]);
+    if (P.shift_out) *P.shift_out = s;
+    if (P.result) P.result->shift = s;
+  }
+}
+
+// dscratch_i32 layout (device): [0, nprob] tile prefix, [nprob+1, 2nprob+1]
+// cluster prefix, then chunk-wave prefix and cluster-wave prefix.
+hipError_t launch_update(const UpdateProb* dprobs, const UpdateProb* hprobs, int nprob,
+                         const int32_t* dpre, hipStream_t st) {
+  int tiles = 0, clusters = 0, chunkwg = 0, clwg = 0;
+  for (int i = 0; i < nprob; ++i) {
+    tiles += hprobs[i].ntiles;
+    clusters += hprobs[i].k;
+    chunkwg += (int)((hprobs[i].n + kUpdChunk - 1) / kUpdChunk + hprobs[i].k + 3) / 4;
+    clwg += (hprobs[i].k + 3) / 4;
+  }
+  const int32_t* pre_tiles = dpre;
+  const int32_t* pre_cl = dpre + (nprob + 1);
+  const int32_t* pre_chunk = dpre + 2 * (nprob + 1);
+  const int32_t* pre_clwg = dpre + 3 * (nprob + 1);
+  if (tiles > 0) hipLaunchKernelGGL(k_upd_hist, dim3(tiles), dim3(256), 0, st, dprobs, pre_tiles, nprob);
+  hipLaunchKernelGGL(k_upd_scan_rel, dim3(clusters), dim3(256), 0, st, dprobs, pre_cl, nprob);
+  hipLaunchKernelGGL(k_upd_scan_cl, dim3(nprob), dim3(1024), 0, st, dprobs);
+  if (tiles > 0) hipLaunchKernelGGL(k_upd_scatter, dim3(tiles), dim3(256), 0, st, dprobs, pre_tiles, nprob);
+  if (chunkwg > 0) hipLaunchKernelGGL(k_upd_chunksum, dim3(chunkwg), dim3(256), 0, st, dprobs, pre_chunk, nprob);
+  hipLaunchKernelGGL(k_upd_finalize, dim3(clwg), dim3(256), 0, st, dprobs, pre_clwg, nprob);
+  hipLaunchKernelGGL(k_upd_shift, dim3(nprob), dim3(256), 0, st, dprobs);
+  return hipGetLastError();
+}
+
+}  // namespace km

@@ -1,0 +1,116 @@
+"""Shared checks for the GPU parity tests (host side only).
+
+The checks compare what the HIP library returned with the CPU oracle on the
+same float32 inputs, following the parity contract:
+
+  (i)   label gate: where the oracle's best centre beats every other centre
+        by more than the per-pair error bounds B, labels must be identical;
+  (ii)  distances within relative 1e-6 of the oracle's FP64 direct value to
+        the returned label, SSE within relative 1e-6, and near-optimality
+        d(i, label) <= d(i, j1) + B(i, label) + B(i, j1) everywhere;
+  (iii) the number of corrected pairs lies between the count of surely
+        corrected pairs and that count plus the ambiguous ones.
+"""
+
+import numpy as np
+
+import oracle
+
+DIST_RTOL = 1e-6
+
+
+def check_assignment(X, C, fmt, alpha, labels, mindist, sse, n_corrected,
+                     min_coverage=0.0, rows=None, check_sandwich=True):
+    """Apply (i)-(iii).  ``rows`` restricts the check to a subset of points
+    (the GPU outputs are then full-length and are indexed by ``rows``).
+    ``fmt`` is 0 (FP16) / 1 (BF16) / 2 (FP32: quantisation is the identity)
+    / None (plain FP64 direct formula everywhere).  Returns a report dict."""
+    X = np.ascontiguousarray(X, dtype=np.float32)
+    C = np.ascontiguousarray(C, dtype=np.float32)
+    if rows is None:
+        rows = np.arange(X.shape[0])
+    Xs = X[rows]
+    lab = np.asarray(labels)[rows].astype(np.int64)
+    if fmt in (0, 1):
+        r = oracle.mp_rows(Xs, C, fmt, alpha)
+        dist, B, cls = r["dist"], r["B"], r["cls"]
+    else:
+        dist = oracle.dist_rows(Xs, C)
+        u32 = oracle.unit_roundoff(2)
+        if fmt is None:  # FP64 direct everywhere, compared in FP64
+            B = 2 * oracle.gamma(X.shape[1] + 2, oracle.unit_roundoff(3)) * dist
+            cls = np.full(dist.shape, -1, dtype=np.int8)
+        else:  # FP32 expanded formula: error bound of thm:dist-exp in FP32
+            xn = (Xs.astype(np.float64) ** 2).sum(1)[:, None]
+            cn = (C.astype(np.float64) ** 2).sum(1)[None, :]
+            P = np.abs(Xs.astype(np.float64)) @ np.abs(C.astype(np.float64)).T
+            g = oracle.gamma(X.shape[1] + 4, 2 * u32)
+            A = g * (xn + cn + 2 * P)
+            B = A + 2 * u32 * dist
+            S = xn + cn
+            if alpha is None or alpha < 0:
+                cls = np.ones(dist.shape, dtype=np.int8)
+            else:
+                margin = dist - alpha * S
+                band = (1 + alpha) * A + 2 * u32 * dist
+                cls = np.where(margin < -band, -1, np.where(margin > band, 1, 0)).astype(np.int8)
+                B = np.where(cls == -1, 2 * u32 * dist, np.where(cls == 1, B, np.maximum(B, 2 * u32 * dist)))
+    m = len(rows)
+    ii = np.arange(m)
+    j1 = np.argmin(dist, axis=1)  # lowest index among exact minimisers
+    gated = oracle.label_gate(dist, B, j1)
+    bad = np.nonzero(gated & (lab != j1))[0]
+    assert bad.size == 0, "gated label mismatch at rows %s (gpu %s, oracle %s)" % (
+        rows[bad[:5]], lab[bad[:5]], j1[bad[:5]])
+    coverage = float(gated.mean())
+    assert coverage >= min_coverage, "gate coverage %.4f < %.4f" % (coverage, min_coverage)
+    d_lab = dist[ii, lab]
+    # near-optimality of the returned label
+    slack = dist[ii, j1] + B[ii, lab] + B[ii, j1]
+    assert np.all(d_lab <= slack * (1 + 1e-12) + 1e-300), "label not near-optimal"
+    if mindist is not None:
+        md = np.asarray(mindist)[rows].astype(np.float64)
+        err = np.abs(md - d_lab)
+        tol = DIST_RTOL * d_lab + 1e-30
+        worst = int(np.argmax(err - tol))
+        assert np.all(err <= tol), "mindist off at row %d: %r vs %r" % (
+            rows[worst], md[worst], d_lab[worst])
+    rep = dict(coverage=coverage, n_rows=m)
+    if sse is not None and len(rows) == X.shape[0]:
+        ref = oracle.pairwise_sum(d_lab)
+        assert abs(sse - ref) <= DIST_RTOL * abs(ref) + 1e-30, "SSE %r vs %r" % (sse, ref)
+        rep["sse_ref"] = ref
+    n_sure = int((cls == -1).sum())
+    n_amb = int((cls == 0).sum())
+    rep.update(n_sure=n_sure, n_amb=n_amb)
+    if check_sandwich and n_corrected is not None and len(rows) == X.shape[0]:
+        assert n_sure <= n_corrected <= n_sure + n_amb, \
+            "corrected %d not in [%d, %d]" % (n_corrected, n_sure, n_sure + n_amb)
+    return rep
+
+
+def check_pairwise(X, C, fmt, alpha, D, flagged):
+    """Per-pair checks on materialised values: flagged pairs are the FP64
+    direct value rounded once to FP32; kept pairs are within A of the
+    quantised distance q (Theorem thm:dist-exp with FP32 arithmetic, P10);
+    surely corrected pairs are flagged and surely kept ones are not."""
+    r = oracle.mp_rows(X, C, fmt, alpha)
+    D = np.asarray(D, dtype=np.float64)
+    fl = np.asarray(flagged).astype(bool)
+    u32 = oracle.unit_roundoff(2)
+    cls = r["cls"]
+    assert not np.any(fl & (cls == 1)), "a surely kept pair was corrected"
+    assert not np.any(~fl & (cls == -1)), "a surely corrected pair was kept"
+    corr = fl
+    err_c = np.abs(D[corr] - r["dist"][corr])
+    assert np.all(err_c <= 2 * u32 * r["dist"][corr] + 1e-30), "corrected value off"
+    kept = ~fl
+    err_k = np.abs(D[kept] - r["q"][kept])
+    # kept values are clamped at zero (max(d^, 0)); the bound covers that
+    assert np.all(err_k <= r["A"][kept] * (1 + 1e-9) + 1e-30), \
+        "kept pair outside the FP32 expanded-formula bound (max excess %.3g)" % (
+            np.max(err_k - r["A"][kept]))
+    rel = np.abs(D - r["dist"]) / np.maximum(r["dist"], 1e-300)
+    return dict(n_flagged=int(fl.sum()), n_sure=int((cls == -1).sum()),
+                n_amb=int((cls == 0).sum()), max_rel_err=float(rel.max()),
+                max_rel_err_kept=float(rel[kept].max()) if kept.any() else 0.0)

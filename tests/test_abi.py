@@ -1,0 +1,64 @@
+"""The C ABI library loads and exports every function include/kmeans.h
+declares (no GPU needed: nothing is called except host-only helpers)."""
+
+import ctypes as ct
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "kmeans.h")
+
+
+def declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    names = re.findall(r"^\s*(?:const\s+)?[a-z_0-9]+\s*\*?\s*(kmeans_[a-z_0-9]+)\s*\(", src, flags=re.M)
+    return sorted(set(names))
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for required in ("kmeans_assign", "kmeans_lloyd", "kmeans_solve_batch",
+                     "kmeans_submit", "kmeans_poll", "kmeans_context_create",
+                     "kmeans_context_destroy", "kmeans_status_string"):
+        assert required in names
+
+
+def test_library_exports_every_declared_symbol():
+    import paper_2407_12208_amd as km
+    path = km.library_path()
+    if not os.path.exists(path):
+        pytest.skip("library not built")
+    L = ct.CDLL(path)
+    missing = [n for n in declared_functions() if not hasattr(L, n)]
+    assert not missing, missing
+    # the binding exposes the same names
+    for n in declared_functions():
+        if n in ("kmeans_context_destroy",):
+            continue
+        assert hasattr(km, n) or n.replace("kmeans_", "") in dir(km), n
+
+
+def test_host_only_helpers():
+    import paper_2407_12208_amd as km
+    if not os.path.exists(km.library_path()):
+        pytest.skip("library not built")
+    assert km.kmeans_status_string(-3) == "non-finite input"
+    assert km.kmeans_status_string(0) == "ok"
+    # threshold computed by the library vs the oracle's independent formula
+    import oracle
+    for fmt, low in ((0, km.KM_LOW_FP16), (1, km.KM_LOW_BF16)):
+        for d in (5, 32, 128):
+            a = km.kmeans_alpha(km.Precision(low, km.KM_ALPHA_PAPER_EQ, 5.0), d)
+            ref = oracle.alpha_value(fmt, d, 5.0, "eq")
+            assert a == pytest.approx(ref, rel=1e-7)
+    with pytest.raises(km.KMeansError):
+        km.kmeans_alpha(km.Precision(km.KM_LOW_FP16, km.KM_ALPHA_PAPER_EQ, 2.0), 8)
+    # context creation without a GPU fails cleanly with a device error
+    import torch
+    if not torch.cuda.is_available():
+        with pytest.raises(km.KMeansError) as e:
+            km.Context(0)
+        assert e.value.code == -5
