@@ -1,0 +1,203 @@
+#!/usr/bin/env python3
+"""Benchmark of the mixed-precision k-means hot path on one MI355X.
+
+Workload: the distance-kernel benchmark shape -- X 1,000,000 x 128 and C
+4,096 x 128, FP32 entries N(0,1) -- with the FP16 -> FP64 mixed-precision
+assignment (threshold rho~ = 5, equation form).  One step is one Lloyd round
+over that input: the fused assignment pass (range check, quantisation, norms,
+MFMA cross term, reliability test, FP64 correction, argmin, FP64 refinement,
+SSE and counters) followed by the centre update (deterministic segmented FP64
+reduction, division, FP32 rounding, largest centre move).  Inputs are
+resident in HBM before timing starts.
+
+Prints ONE JSON line.  Extra keys report the assignment kernel alone, the
+plain FP64 direct-formula kernel on the same input, the fallback ratio, the
+single-solve Lloyd rate (20,000 x 32, k = 16) and, as `cpu_baseline`, the
+CPU oracle timed on a bounded sample of the same workload.
+"""
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+MFMA_FP16_PEAK_TFLOPS = 2500.0   # MI355X dense FP16 matrix peak
+FP64_PEAK_TFLOPS = 78.6          # MI355X FP64 vector peak
+HBM_PEAK_GBS = 8000.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-extra", action="store_true", help="skip the extra measurements")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--calib-copy-mib", type=int, default=0,
+                    help="also run a plain device copy of this size (counter calibration)")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(the hot path would shard rows of X across GPUs; see the design notes). "
+              "Run with --gpus 1.", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_2407_12208_amd as km
+    import workloads as W
+
+    cfg = W.DIST_BENCH
+    n, d, k = cfg["n"], cfg["d"], cfg["k"]
+    log("generating X %dx%d and C %dx%d (seed %d)" % (n, d, k, d, cfg["seed"]))
+    Xh, Ch = W.gaussian_pair(n, k, d, cfg["seed"])
+    X = torch.from_numpy(Xh).cuda()
+    Ca = torch.from_numpy(Ch).cuda()
+    Cb = torch.empty_like(Ca)
+    labels = torch.empty(n, dtype=torch.int32, device="cuda")
+    shift = torch.empty(1, dtype=torch.float64, device="cuda")
+    ctx = km.Context(0)
+    prec = km.Precision(km.KM_LOW_FP16, km.KM_ALPHA_PAPER_EQ, 5.0)
+    stream = torch.cuda.current_stream()
+
+    def step(c_in, c_out):
+        km.kmeans_assign(ctx, X, c_in, prec, labels=labels, stats=False, stream=stream)
+        km.kmeans_update(ctx, X, labels, c_in, C_new=c_out, shift=shift, stream=stream)
+
+    bufs = [Ca, Cb]
+    for i in range(args.warmup):
+        step(bufs[i & 1], bufs[(i + 1) & 1])
+    torch.cuda.synchronize()
+    km.kmeans_timing_enable(ctx, True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        step(bufs[(args.warmup + i) & 1], bufs[(args.warmup + i + 1) & 1])
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    kern_ms = km.kmeans_timing_read(ctx)
+    km.kmeans_timing_enable(ctx, False)
+    elapsed = t1 - t0
+    ms_per_step = 1e3 * elapsed / args.steps
+    pairs = float(n) * k
+    value = pairs * args.steps / elapsed
+    kern_avg_ms = float(np.mean(kern_ms)) if kern_ms else float("nan")
+    flops = 2.0 * n * k * d
+    achieved = flops / (kern_avg_ms * 1e-3) / 1e12
+    log("step %.3f ms, assign kernel %.3f ms (%d launches), %.1f TFLOP/s" %
+        (ms_per_step, kern_avg_ms, len(kern_ms), achieved))
+
+    out = {
+        "metric": "assign distance-pairs/s & Lloyd iters/s vs FP64 GPU baseline; p50/p99 solve latency",
+        "value": value,
+        "unit": "pairs/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f16+f64",
+        "data": "synthetic",
+        "config": {"workload": "distance-kernel benchmark: X 1e6x128, C 4096x128, N(0,1) FP32; "
+                               "one Lloyd round (mixed FP16->FP64 assign + centre update)",
+                   "n": n, "d": d, "k": k, "low": "fp16", "high": "fp64",
+                   "alpha_form": "equation (2 rho gamma)", "rho": 5.0},
+        "roofline": {"bound": "mfma", "achieved": achieved, "peak": MFMA_FP16_PEAK_TFLOPS,
+                     "unit": "TFLOP/s", "frac": achieved / MFMA_FP16_PEAK_TFLOPS,
+                     "traffic": None,
+                     "kernel": "k_assign_mfma<LowF16,128,2,0,true>",
+                     "kernel_avg_ms": kern_avg_ms,
+                     "algorithmic_flops_per_launch": flops},
+    }
+
+    if not args.no_extra:
+        extra = {}
+        # fallback ratio and SSE of one pass (stats force a wait)
+        _, _, _, st = km.kmeans_assign(ctx, X, Ca, prec, labels=labels, stats=True)
+        extra["eta"] = st["n_corrected"] / st["n_pairs"]
+        extra["alpha_used"] = st["alpha_used"]
+        extra["assign_kernel_pairs_per_s"] = pairs / (kern_avg_ms * 1e-3)
+        # plain FP64 direct-formula kernel on the same input
+        p64 = km.Precision(km.KM_EXACT64)
+        km.kmeans_timing_enable(ctx, True)
+        for _ in range(3):
+            km.kmeans_assign(ctx, X, Ca, p64, labels=labels, stats=False)
+        t64 = km.kmeans_timing_read(ctx)
+        km.kmeans_timing_enable(ctx, False)
+        ms64 = float(np.median(t64))
+        extra["fp64_direct_kernel_ms"] = ms64
+        extra["fp64_direct_pairs_per_s"] = pairs / (ms64 * 1e-3)
+        extra["speedup_assign_vs_fp64_direct"] = ms64 / kern_avg_ms
+        extra["fp64_direct_frac_of_fp64_peak"] = (3.0 * n * k * d / (ms64 * 1e-3) / 1e12) / FP64_PEAK_TFLOPS
+        # single Lloyd solve: 20,000 x 32, 16 blobs, 20 rounds + final pass
+        cs = W.LLOYD_SMALL
+        Xs, _, _ = W.blobs(cs["n"], cs["d"], cs["k"], cs["seed"])
+        C0 = W.init_centroids(Xs, cs["k"], cs["init_seed"])
+        Xs_d = torch.from_numpy(Xs).cuda()
+        res = {}
+        for name, pr in (("mixed_fp16_fp64", prec), ("fp64_direct", p64)):
+            Cs = torch.from_numpy(C0).cuda()
+            km.kmeans_lloyd(ctx, Xs_d, Cs, cs["iters"], prec=pr, stats=False)
+            torch.cuda.synchronize()
+            reps = 5
+            ts = time.perf_counter()
+            for _ in range(reps):
+                Cs.copy_(torch.from_numpy(C0).cuda())
+                km.kmeans_lloyd(ctx, Xs_d, Cs, cs["iters"], prec=pr, stats=False)
+            torch.cuda.synchronize()
+            dt = (time.perf_counter() - ts) / reps
+            res[name] = cs["iters"] / dt
+        extra["lloyd_small_iters_per_s"] = res["mixed_fp16_fp64"]
+        extra["lloyd_small_iters_per_s_fp64_direct"] = res["fp64_direct"]
+        out["extra"] = extra
+        log("extra: %s" % json.dumps(extra))
+
+    if args.calib_copy_mib > 0:
+        nbytes = args.calib_copy_mib << 20
+        a = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda").fill_(1.0)
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        out["calib_copy_bytes"] = nbytes
+
+    if not args.no_cpu:
+        import oracle
+        threads = oracle.num_threads()
+        g = np.random.default_rng(4)
+        m = 64
+        rows = np.sort(g.choice(n, size=m, replace=False))
+        ts = time.perf_counter()
+        oracle.assign(Xh[rows], Ch)
+        dt = time.perf_counter() - ts
+        m = int(min(n, max(64, m * args.cpu_seconds / max(dt, 1e-3))))
+        rows = np.sort(g.choice(n, size=m, replace=False))
+        ts = time.perf_counter()
+        oracle.assign(Xh[rows], Ch)
+        dt = time.perf_counter() - ts
+        out["cpu_baseline"] = {
+            "value": float(m) * k / dt, "unit": "pairs/s", "cores": threads,
+            "kind": "oracle",
+            "sample": "%d random rows of X against all %d centres (FP64 direct formula, "
+                      "exact argmin), %.1f s" % (m, k, dt)}
+        log("cpu oracle: %d rows in %.2f s on %d threads" % (m, dt, threads))
+
+    ctx.close()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -228,6 +228,17 @@ int32_t kmeans_cancel(km_server *srv, uint64_t ticket);
  * and frees the arena. */
 int32_t kmeans_server_destroy(km_server *srv);
 
+/* ---- kernel timing (benchmarks) ----------------------------------------------
+ * While enabled, every launch of the assignment kernel (the fused
+ * mixed-precision kernel or the FP64 direct kernel) is bracketed by two HIP
+ * events recorded on the launch's stream.  kmeans_timing_enable resets the
+ * record.  kmeans_timing_read waits for the recorded events and copies up to
+ * `max` durations (milliseconds, launch order) into ms_out; *count receives
+ * the number recorded. */
+int32_t kmeans_timing_enable(km_context *ctx, int32_t enable);
+int32_t kmeans_timing_read(km_context *ctx, float *ms_out, int32_t max,
+                           int32_t *count);
+
 /* Human-readable text for a status code (static storage). */
 const char *kmeans_status_string(int32_t status);
 

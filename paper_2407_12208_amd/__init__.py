@@ -22,6 +22,7 @@ __all__ = [
     "kmeans_lloyd", "kmeans_solve_batch", "kmeans_pairwise", "kmeans_quantize",
     "kmeans_alpha", "kmeans_status_string", "Server", "kmeans_server_create",
     "kmeans_submit", "kmeans_poll", "kmeans_cancel", "kmeans_server_destroy",
+    "kmeans_timing_enable", "kmeans_timing_read",
 ]
 
 KM_LOW_FP16, KM_LOW_BF16, KM_LOW_FP32, KM_EXACT64 = 0, 1, 2, 3
@@ -107,6 +108,8 @@ def lib():
                 "kmeans_poll": [P, ct.c_uint64, i32],
                 "kmeans_cancel": [P, ct.c_uint64],
                 "kmeans_server_destroy": [P],
+                "kmeans_timing_enable": [P, i32],
+                "kmeans_timing_read": [P, ct.POINTER(ct.c_float), i32, ct.POINTER(i32)],
             }
             for name, args in sig.items():
                 fn = getattr(L, name)
@@ -203,6 +206,21 @@ class Context:
 
 def kmeans_context_create(device: int = 0) -> Context:
     return Context(device)
+
+
+def kmeans_timing_enable(ctx: Context, enable: bool = True) -> None:
+    _check(lib().kmeans_timing_enable(ctx.handle, 1 if enable else 0),
+           "kmeans_timing_enable")
+
+
+def kmeans_timing_read(ctx: Context, max_count: int = 4096):
+    """Durations (ms) of the assignment-kernel launches recorded since
+    kmeans_timing_enable, in launch order."""
+    buf = (ct.c_float * max_count)()
+    cnt = ct.c_int32()
+    _check(lib().kmeans_timing_read(ctx.handle, buf, max_count, ct.byref(cnt)),
+           "kmeans_timing_read")
+    return [buf[i] for i in range(min(cnt.value, max_count))]
 
 
 def kmeans_alpha(prec=None, d: int = 128) -> float:

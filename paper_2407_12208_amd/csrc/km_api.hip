@@ -144,12 +144,21 @@ static std::vector<int32_t> prefix(const std::vector<int>& counts) {
 hipError_t run_prep(km_context_impl* ctx, int low, const std::vector<PrepProb>& probs,
                     const std::vector<int>& kpads, hipStream_t st) {
   std::vector<int> wgs(kpads.size());
-  for (size_t i = 0; i < kpads.size(); ++i) wgs[i] = (kpads[i] + 255) / 256;
+  for (size_t i = 0; i < kpads.size(); ++i) wgs[i] = (kpads[i] + 3) / 4;  // one wave per centre
   std::vector<int32_t> pre = prefix(wgs);
   void* dp = ctx->up.put(probs.data(), probs.size() * sizeof(PrepProb), st);
   void* ds = ctx->up.put(pre.data(), pre.size() * sizeof(int32_t), st);
   if (!dp || !ds) return hipErrorOutOfMemory;
   return launch_prep(low, (const PrepProb*)dp, (const int32_t*)ds, (int)probs.size(), pre.back(), st);
+}
+
+hipEvent_t km_context_impl::timing_event(int i) {
+  while ((int)ev_pool.size() <= i) {
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    ev_pool.push_back(e);
+  }
+  return ev_pool[i];
 }
 
 hipError_t run_assign(km_context_impl* ctx, const AssignPlan& shape, int mode,
@@ -159,17 +168,32 @@ hipError_t run_assign(km_context_impl* ctx, const AssignPlan& shape, int mode,
   void* dp = ctx->up.put(probs.data(), probs.size() * sizeof(AssignProb), st);
   void* ds = ctx->up.put(pre.data(), pre.size() * sizeof(int32_t), st);
   if (!dp || !ds) return hipErrorOutOfMemory;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (ctx->timing) {
+    e0 = ctx->timing_event(2 * ctx->ev_used);
+    e1 = ctx->timing_event(2 * ctx->ev_used + 1);
+    if (!e0 || !e1) return hipErrorOutOfMemory;
+    hipError_t e = hipEventRecord(e0, st);
+    if (e != hipSuccess) return e;
+  }
+  hipError_t e = hipErrorInvalidValue;
   switch (shape.route) {
     case Route::Mfma:
     case Route::MfmaNoFallback:
-      return launch_assign_mfma(shape.low, shape.DP, mode, shape.route == Route::Mfma,
-                                (const AssignProb*)dp, (const int32_t*)ds, (int)probs.size(), pre.back(), st);
+      e = launch_assign_mfma(shape.low, shape.DP, mode, shape.route == Route::Mfma, (const AssignProb*)dp,
+                             (const int32_t*)ds, (int)probs.size(), pre.back(), st);
+      break;
     case Route::Direct64Exact:
     case Route::Direct64All:
-      return launch_assign_direct64(shape.route == Route::Direct64Exact, mode, (const AssignProb*)dp,
-                                    (const int32_t*)ds, (int)probs.size(), pre.back(), st);
+      e = launch_assign_direct64(shape.route == Route::Direct64Exact, mode, (const AssignProb*)dp,
+                                 (const int32_t*)ds, (int)probs.size(), pre.back(), st);
+      break;
   }
-  return hipErrorInvalidValue;
+  if (e == hipSuccess && ctx->timing) {
+    e = hipEventRecord(e1, st);
+    ctx->ev_used += 1;
+  }
+  return e;
 }
 
 hipError_t run_reduce(km_context_impl* ctx, const std::vector<ReduceProb>& probs, hipStream_t st) {
@@ -295,10 +319,31 @@ int32_t kmeans_context_create(int32_t device, km_context** out) {
   return KM_OK;
 }
 
+int32_t kmeans_timing_enable(km_context* c, int32_t enable) {
+  if (!c) return KM_ERR_ARG;
+  c->timing = enable != 0;
+  c->ev_used = 0;
+  return KM_OK;
+}
+
+int32_t kmeans_timing_read(km_context* c, float* ms_out, int32_t max, int32_t* count) {
+  if (!c || (!ms_out && max > 0) || max < 0) return KM_ERR_ARG;
+  const int n = c->ev_used;
+  for (int i = 0; i < n && i < max; ++i) {
+    if (hipEventSynchronize(c->ev_pool[2 * i + 1]) != hipSuccess) return KM_ERR_DEVICE;
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, c->ev_pool[2 * i], c->ev_pool[2 * i + 1]) != hipSuccess) return KM_ERR_DEVICE;
+    ms_out[i] = ms;
+  }
+  if (count) *count = n;
+  return KM_OK;
+}
+
 int32_t kmeans_context_destroy(km_context* c) {
   if (!c) return KM_ERR_ARG;
   (void)hipSetDevice(c->device);
   (void)hipDeviceSynchronize();
+  for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
   c->up.destroy();
   if (c->arena.base) (void)hipFree(c->arena.base);
   if (c->h_scalar) (void)hipHostFree(c->h_scalar);

@@ -47,10 +47,13 @@ __device__ inline void raise_status(int* status, int bits) {
 }
 
 // ---------------------------------------------------------------------------
-// Centre preparation.  One thread per (padded) centre row.
+// Centre preparation.  One wave per (padded) centre row, lanes over the
+// coordinates.
 //   Cq[j, 0:DP]  = RNE_low(C[j, 0:d]), zero padded
-//   nc_j         = sum_l Cq[j,l]^2 in FP32, index order (norm of the
-//                  quantised centre, as the expanded formula requires)
+//   nc_j         = sum_l Cq[j,l]^2 in FP32 (each lane sums its coordinates
+//                  l = lane, lane+64, ... in order, then a fixed butterfly):
+//                  the norm of the quantised centre, as the expanded formula
+//                  requires
 //   cinit[j]     = -nc_j / 2          (accumulator start of the cross term)
 //   ca[j]        = alpha * nc_j / 2   (centre part of the reliability test)
 // Padded rows j >= k: cinit = -inf, ca = 0, so they never win and never fail
@@ -61,30 +64,36 @@ __global__ void __launch_bounds__(256)
 k_prep_centroids(const PrepProb* __restrict__ probs, const int32_t* __restrict__ wg_start, int nprob) {
   const int pi = find_problem(wg_start, nprob, blockIdx.x);
   const PrepProb& P = probs[pi];
-  const int j = (blockIdx.x - wg_start[pi]) * 256 + threadIdx.x;
+  const int lane = threadIdx.x & 63;
+  const int j = (blockIdx.x - wg_start[pi]) * 4 + (threadIdx.x >> 6);
   if (j >= P.k_pad) return;
   typename L::S* out = reinterpret_cast<typename L::S*>(P.Cq) + (int64_t)j * P.DP;
   int bad = 0;
-  if (j < P.k) {
-    const float* c = P.C + (int64_t)j * P.d;
-    float s = 0.0f;
-    for (int l = 0; l < P.d; ++l) {
-      float v = c[l];
+  float s = 0.0f;
+  const bool valid = j < P.k;
+  for (int l = lane; l < P.DP; l += 64) {
+    float v = 0.0f;
+    if (valid && l < P.d) {
+      v = P.C[(int64_t)j * P.d + l];
       if (!__builtin_isfinite(v)) bad |= kStatusNonFinite;
       if (L::kHasRange && __builtin_fabsf(v) >= L::kOverflow) bad |= kStatusRange;
-      typename L::S q = L::cvt(v);
-      out[l] = q;
-      float f = L::tof(q);
-      s = __builtin_fmaf(f, f, s);
     }
-    for (int l = P.d; l < P.DP; ++l) out[l] = L::cvt(0.0f);
-    float hc = 0.5f * s;
-    P.cinit[j] = -hc;
-    P.ca[j] = P.alpha * hc;
-  } else {
-    for (int l = 0; l < P.DP; ++l) out[l] = L::cvt(0.0f);
-    P.cinit[j] = -__builtin_inff();
-    P.ca[j] = 0.0f;
+    const typename L::S q = L::cvt(v);
+    out[l] = q;
+    const float f = L::tof(q);
+    s = __builtin_fmaf(f, f, s);
+  }
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) s += __shfl_xor(s, o, kWave);
+  if (lane == 0) {
+    if (valid) {
+      const float hc = 0.5f * s;
+      P.cinit[j] = -hc;
+      P.ca[j] = P.alpha * hc;
+    } else {
+      P.cinit[j] = -__builtin_inff();
+      P.ca[j] = 0.0f;
+    }
   }
   raise_status(P.status, bad);
 }

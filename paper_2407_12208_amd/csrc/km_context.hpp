@@ -77,6 +77,11 @@ struct km_context_impl {
   double* h_scalar = nullptr;     // pinned: shift read-back
   KResult* h_result = nullptr;    // pinned: result read-back (up to kMaxResults)
   static constexpr int kMaxResults = 4096;
+  // kernel timing
+  bool timing = false;
+  std::vector<hipEvent_t> ev_pool;  // pairs: [2i] start, [2i+1] stop
+  int ev_used = 0;                  // pairs recorded since enable
+  hipEvent_t timing_event(int i);
 };
 
 // Threshold alpha for (prec, d): -1 = no fallback, +inf = always correct.

@@ -1,0 +1,96 @@
+"""Parity at the full sizes of the benchmark workloads, in the launch
+configuration bench.py times, on sampled rows the oracle can compute one by
+one."""
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+from tests.gpu_helpers import check_assignment, check_pairwise
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+km = pytest.importorskip("paper_2407_12208_amd")
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = km.Context(0)
+    yield c
+    c.close()
+
+
+def host(t):
+    return t.cpu().numpy()
+
+
+@pytest.fixture(scope="module")
+def dist_bench():
+    cfg = W.DIST_BENCH
+    X, C = W.gaussian_pair(cfg["n"], cfg["k"], cfg["d"], cfg["seed"])
+    return X, C
+
+
+def test_dist_bench_full_fp16(ctx, dist_bench):
+    X, C = dist_bench
+    p = km.Precision(km.KM_LOW_FP16, km.KM_ALPHA_PAPER_EQ, 5.0)
+    Xd = torch.from_numpy(X).cuda()
+    Cd = torch.from_numpy(C).cuda()
+    labels, mind, sse, st = km.kmeans_assign(ctx, Xd, Cd, p, mindist=True, sse=True)
+    rows = np.sort(np.random.default_rng(11).choice(len(X), 384, replace=False))
+    rep = check_assignment(X, C, 0, st["alpha_used"], host(labels), host(mind), None, None,
+                           min_coverage=0.99, rows=rows)
+    # corrected-pair sandwich and per-pair values on the sampled rows (same
+    # kernel arithmetic, materialised)
+    D, fl = km.kmeans_pairwise(ctx, Xd[torch.from_numpy(rows).cuda()].contiguous(), Cd, p,
+                               flagged=True)
+    prep = check_pairwise(X[rows], C, 0, st["alpha_used"], host(D), host(fl))
+    eta = st["n_corrected"] / st["n_pairs"]
+    assert 0 < eta < 1e-3
+    # SSE equals the sum of the reported FP64 distances (within FP32 rounding)
+    assert float(host(sse)[0]) == pytest.approx(host(mind).astype(np.float64).sum(), rel=1e-6)
+    print("gate coverage %.4f, eta %.3g, max rel err (kept) %.3g"
+          % (rep["coverage"], eta, prep["max_rel_err_kept"]))
+
+
+def test_dist_bench_full_fp64_direct(ctx, dist_bench):
+    X, C = dist_bench
+    Xd = torch.from_numpy(X).cuda()
+    Cd = torch.from_numpy(C).cuda()
+    labels, mind, _, st = km.kmeans_assign(ctx, Xd, Cd, km.Precision(km.KM_EXACT64), mindist=True)
+    rows = np.sort(np.random.default_rng(12).choice(len(X), 256, replace=False))
+    check_assignment(X, C, None, None, host(labels), host(mind), None, None,
+                     min_coverage=0.999, rows=rows)
+
+
+def test_dist_bench_cancellation_variant(ctx):
+    # +1e3 offset, spread 1e-2: every pair fails the test; smaller n keeps the
+    # fully corrected pass short
+    X, C = W.cancellation_pair(100_000, 4096, 128, seed=1002)
+    Xd = torch.from_numpy(X).cuda()
+    Cd = torch.from_numpy(C).cuda()
+    for low, fmt in ((km.KM_LOW_FP16, 0), (km.KM_LOW_BF16, 1)):
+        p = km.Precision(low, km.KM_ALPHA_PAPER_EQ, 5.0)
+        labels, mind, _, st = km.kmeans_assign(ctx, Xd, Cd, p, mindist=True)
+        assert st["n_corrected"] == st["n_pairs"]
+        rows = np.sort(np.random.default_rng(13).choice(len(X), 128, replace=False))
+        check_assignment(X, C, fmt, st["alpha_used"], host(labels), host(mind), None, None,
+                         min_coverage=0.99, rows=rows)
+
+
+def test_large_clustering_full_assign(ctx):
+    cfg = W.LLOYD_LARGE
+    X, _, _ = W.blobs(cfg["n"], cfg["d"], cfg["k"], cfg["seed"], center_box=(-50, 50),
+                      std_range=(0.1, 2.0))
+    C0 = W.init_centroids(X, cfg["k"], cfg["init_seed"])
+    Xd = torch.from_numpy(X).cuda()
+    rows = np.sort(np.random.default_rng(14).choice(len(X), 512, replace=False))
+    for low, fmt in ((km.KM_LOW_FP16, 0), (km.KM_LOW_BF16, 1), (km.KM_LOW_FP32, 2)):
+        p = km.Precision(low, km.KM_ALPHA_PAPER_EQ, 5.0)
+        labels, mind, _, st = km.kmeans_assign(ctx, Xd, torch.from_numpy(C0).cuda(), p, mindist=True)
+        # at random initial centres several centres share a blob: more near
+        # ties than at convergence, so the gate covers fewer points
+        check_assignment(X, C0, fmt, st["alpha_used"], host(labels), host(mind), None, None,
+                         min_coverage=0.95, rows=rows)
