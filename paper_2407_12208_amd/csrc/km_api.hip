@@ -232,15 +232,16 @@ UpdateProb carve_update(Arena& a, int64_t n, int d, int k) {
 
 hipError_t run_update(km_context_impl* ctx, const std::vector<UpdateProb>& probs, hipStream_t st) {
   const int np = (int)probs.size();
-  std::vector<int> tiles(np), cl(np), chunkwg(np), clwg(np);
+  std::vector<int> tiles(np), cl(np), chunkwg(np), clwg(np), scatwg(np);
   for (int i = 0; i < np; ++i) {
     tiles[i] = probs[i].ntiles;
     cl[i] = probs[i].k;
     chunkwg[i] = (int)(((probs[i].n + kUpdChunk - 1) / kUpdChunk + probs[i].k + 3) / 4);
     clwg[i] = (probs[i].k + 3) / 4;
+    scatwg[i] = (probs[i].ntiles + 3) / 4;
   }
   std::vector<int32_t> pre;
-  for (auto* v : {&tiles, &cl, &chunkwg, &clwg}) {
+  for (auto* v : {&tiles, &cl, &chunkwg, &clwg, &scatwg}) {
     std::vector<int32_t> p = prefix(*v);
     pre.insert(pre.end(), p.begin(), p.end());
   }

@@ -25,6 +25,22 @@
 
 namespace km {
 
+__device__ __noinline__ double sqdist64_call(const float* __restrict__ x, const float* __restrict__ c, int d) {
+  return sqdist64(x, c, d);
+}
+
+// Maximum of the 16 accumulator registers (a v_max3 tree).
+__device__ inline float max16(const f32x16& v) {
+  const float a = __builtin_fmaxf(__builtin_fmaxf(v[0], v[1]), v[2]);
+  const float b = __builtin_fmaxf(__builtin_fmaxf(v[3], v[4]), v[5]);
+  const float c = __builtin_fmaxf(__builtin_fmaxf(v[6], v[7]), v[8]);
+  const float e = __builtin_fmaxf(__builtin_fmaxf(v[9], v[10]), v[11]);
+  const float f = __builtin_fmaxf(__builtin_fmaxf(v[12], v[13]), v[14]);
+  const float g = __builtin_fmaxf(__builtin_fmaxf(a, b), c);
+  const float h = __builtin_fmaxf(__builtin_fmaxf(e, f), v[15]);
+  return __builtin_fmaxf(g, h);
+}
+
 // Problem index of workgroup b: largest p with wg_start[p] <= b.
 __device__ inline int find_problem(const int32_t* __restrict__ wg_start, int nprob, int b) {
   int lo = 0, hi = nprob - 1;
@@ -161,6 +177,8 @@ k_assign_mfma(const AssignProb* __restrict__ probs, const int32_t* __restrict__ 
   const int pw = wave * NB * 32;  // first point of this wave within the tile
   int bad = 0;
   const bool vec4 = ((d & 3) == 0) && ((((uintptr_t)P.X) & 15) == 0);
+  // full tile, no coordinate padding: unconditional streaming loads
+  const bool fast = vec4 && d == DP && nvalid == Cfg::kPts;
 #pragma unroll
   for (int cb = 0; cb < NB; ++cb) {
     const int pl = pw + cb * 32 + (lane & 31);
@@ -172,7 +190,13 @@ k_assign_mfma(const AssignProb* __restrict__ probs, const int32_t* __restrict__ 
       const int o = s * L::KS + (lane >> 5) * L::KV;
       float v[L::KV];
       if constexpr (L::KV % 4 == 0) {
-        if (vec4) {
+        if (fast) {
+#pragma unroll
+          for (int u = 0; u < L::KV; u += 4) {
+            const f32x4 q = __builtin_nontemporal_load(reinterpret_cast<const f32x4*>(xr + o + u));
+            v[u] = q[0]; v[u + 1] = q[1]; v[u + 2] = q[2]; v[u + 3] = q[3];
+          }
+        } else if (vec4) {
 #pragma unroll
           for (int u = 0; u < L::KV; u += 4) {
             float4 q = make_float4(0.f, 0.f, 0.f, 0.f);
@@ -208,19 +232,58 @@ k_assign_mfma(const AssignProb* __restrict__ probs, const int32_t* __restrict__ 
 
   S* const sc0 = reinterpret_cast<S*>(smem);  // two buffers of CT rows
 
-  // running state per column block: best kept (largest W), best corrected
+  // running state per column block: best kept value (largest W), the block
+  // where it occurred and a copy of that block's 16 accumulator values (the
+  // index inside the block is recovered once, after the sweep); best
+  // corrected pair (smallest FP64-direct value rounded to FP32)
   float bw[NB];
-  int bj[NB];
+  int bb[NB];
+  f32x16 sv[NB];
   float cd[NB];
   int cj[NB];
 #pragma unroll
   for (int cb = 0; cb < NB; ++cb) {
     bw[cb] = -__builtin_inff();
-    bj[cb] = -1;
+    bb[cb] = -1;
     cd[cb] = __builtin_inff();
     cj[cb] = -1;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) sv[cb][r] = -__builtin_inff();
   }
   unsigned long long ncorr = 0;
+
+  // per-lane queue of flagged pairs (centre index | column block << 24)
+  constexpr int kQueue = 12;
+  __shared__ int s_q[FALLBACK ? kQueue * 256 : 1];
+  int qn = 0;
+  auto flush_queue = [&]() {
+    if constexpr (FALLBACK) {
+      for (int q = 0; q < qn; ++q) {
+        const int e = s_q[q * 256 + tid];
+        const int j = e & 0xffffff;
+        const int cbq = e >> 24;
+        const int pl = pw + cbq * 32 + (lane & 31);
+        const double dd = sqdist64(P.X + (p0 + pl) * d, P.C + (int64_t)j * d, d);
+        const float df = (float)dd;
+        ncorr += 1;
+#pragma unroll
+        for (int cb = 0; cb < NB; ++cb) {
+          if (cb != cbq) continue;
+          if constexpr (MODE == 0) {
+            if (df < cd[cb] || (df == cd[cb] && j < cj[cb])) {
+              cd[cb] = df;
+              cj[cb] = j;
+            }
+          } else {
+            const int64_t o = (p0 + pl) * (int64_t)P.k + j;
+            P.D[o] = df;
+            if (P.flagged) P.flagged[o] = 1;
+          }
+        }
+      }
+      qn = 0;
+    }
+  };
 
   const int kpad = P.k_pad;
   const int ntile = (kpad + CT - 1) / CT;
@@ -276,49 +339,76 @@ k_assign_mfma(const AssignProb* __restrict__ probs, const int32_t* __restrict__ 
       for (int cb = 0; cb < NB; ++cb) fmask[bk][cb] = 0;
     for (int bk = 0; bk < rows / 32; ++bk) {
       const int jb = t * CT + bk * 32;  // first centre of this 32-block
-      f32x16 ci;
-#pragma unroll
-      for (int r = 0; r < 16; ++r) ci[r] = s_cinit[buf][bk * 32 + acc_row(r, lane)];
-      const float* cab = &s_ca[buf][bk * 32];
-      f32x16 acc[NB];
-#pragma unroll
-      for (int cb = 0; cb < NB; ++cb) acc[cb] = ci;
+      // all A fragments of the block first (their LDS latency overlaps)
+      typename L::frag af[Cfg::kSteps];
       const S* arow = sc0 + buf * CT * LD + (bk * 32 + (lane & 31)) * LD + (lane >> 5) * L::KV;
 #pragma unroll
       for (int s = 0; s < Cfg::kSteps; ++s) {
-        typename L::frag a;
-        if constexpr (L::KV == 1) a = arow[s * L::KS];
-        else a = *reinterpret_cast<const typename L::frag*>(arow + s * L::KS);
-#pragma unroll
-        for (int cb = 0; cb < NB; ++cb) acc[cb] = L::mfma(a, bfr[cb][s], acc[cb]);
+        if constexpr (L::KV == 1) af[s] = arow[s * L::KS];
+        else af[s] = *reinterpret_cast<const typename L::frag*>(arow + s * L::KS);
       }
+      f32x16 acc[NB];
+      {
+        f32x16 ci;
+#pragma unroll
+        for (int r = 0; r < 16; ++r) ci[r] = s_cinit[buf][bk * 32 + acc_row(r, lane)];
+#pragma unroll
+        for (int cb = 0; cb < NB; ++cb) acc[cb] = L::mfma(af[0], bfr[cb][0], ci);
+      }
+#pragma unroll
+      for (int s = 1; s < Cfg::kSteps; ++s)
+#pragma unroll
+        for (int cb = 0; cb < NB; ++cb) acc[cb] = L::mfma(af[s], bfr[cb][s], acc[cb]);
+
       // ---- epilogue ----
+      f32x16 cav;
+      if constexpr (FALLBACK) {
+#pragma unroll
+        for (int r = 0; r < 16; ++r) cav[r] = s_ca[buf][bk * 32 + acc_row(r, lane)];
+      }
 #pragma unroll
       for (int cb = 0; cb < NB; ++cb) {
-        const int pl = pw + cb * 32 + (lane & 31);
-        uint32_t fm = 0;  // flagged accumulator registers of this lane
+        f32x16 w = acc[cb];
+        if constexpr (MODE == 0) {
+          if constexpr (FALLBACK) {
+            // any pair failing the test  W + ca >= hx  in this block?
+            f32x16 tv = w + cav;
+            const float tm = max16(tv);
+            if (__ballot(tm >= hx[cb])) {  // rare: wave-uniform slow path
+              uint32_t fm = 0;
 #pragma unroll
-        for (int r = 0; r < 16; ++r) {
-          const float w = acc[cb][r];
-          const bool flag = FALLBACK && (w + cab[acc_row(r, lane)] >= hx[cb]);
-          if (FALLBACK) fm |= (uint32_t)flag << r;
-          if constexpr (MODE == 0) {
-            const bool better = !flag && (w > bw[cb]);
-            bw[cb] = better ? w : bw[cb];
-            bj[cb] = better ? jb + acc_row(r, lane) : bj[cb];
-          } else {
+              for (int r = 0; r < 16; ++r) {
+                const bool f = tv[r] >= hx[cb];
+                fm |= (uint32_t)f << r;
+                w[r] = f ? -__builtin_inff() : w[r];
+              }
+              fmask[bk][cb] = fm;
+            }
+          }
+          const float wm = max16(w);
+          const bool imp = wm > bw[cb];  // strict: the earlier block keeps ties
+          bw[cb] = imp ? wm : bw[cb];
+          bb[cb] = imp ? jb : bb[cb];
+#pragma unroll
+          for (int r = 0; r < 16; ++r) sv[cb][r] = imp ? w[r] : sv[cb][r];
+        } else {
+          const int pl = pw + cb * 32 + (lane & 31);
+#pragma unroll
+          for (int r = 0; r < 16; ++r) {
             const int j = jb + acc_row(r, lane);
+            const bool flag = FALLBACK && (w[r] + cav[r] >= hx[cb]);
+            if (flag) fmask[bk][cb] |= 1u << r;
             if (!flag && pl < nvalid && j < P.k) {
               const int64_t o = (p0 + pl) * (int64_t)P.k + j;
-              P.D[o] = __builtin_fmaxf(nx[cb] - 2.0f * w, 0.0f);
+              P.D[o] = __builtin_fmaxf(nx[cb] - 2.0f * w[r], 0.0f);
               if (P.flagged) P.flagged[o] = 0;
             }
           }
         }
-        if (FALLBACK) fmask[bk][cb] = fm;
       }
     }
-    // flagged pairs of this tile: FP64 direct formula from the FP32 originals
+    // queue this tile's flagged pairs; they are corrected in batches (one
+    // memory round trip per batch instead of one per tile)
     if constexpr (FALLBACK) {
 #pragma unroll
       for (int bk = 0; bk < 2; ++bk)
@@ -326,43 +416,45 @@ k_assign_mfma(const AssignProb* __restrict__ probs, const int32_t* __restrict__ 
         for (int cb = 0; cb < NB; ++cb) {
           uint32_t fm = fmask[bk][cb];
           const int pl = pw + cb * 32 + (lane & 31);
-          if (!fm || pl >= nvalid) continue;
-          const float* xr = P.X + (p0 + pl) * d;
-          do {
+          if (pl >= nvalid) fm = 0;
+          while (fm) {
             const int r = __builtin_ctz(fm);
             fm &= fm - 1;
             const int j = t * CT + bk * 32 + acc_row(r, lane);
-            if (j >= P.k) continue;
-            const double dd = sqdist64(xr, P.C + (int64_t)j * d, d);
-            const float df = (float)dd;
-            ncorr += 1;
-            if constexpr (MODE == 0) {
-              if (df < cd[cb] || (df == cd[cb] && j < cj[cb])) {
-                cd[cb] = df;
-                cj[cb] = j;
+            if (j < P.k) {
+              if (qn == kQueue) {  // full: flush this lane's queue first
+                flush_queue();
               }
-            } else {
-              const int64_t o = (p0 + pl) * (int64_t)P.k + j;
-              P.D[o] = df;
-              if (P.flagged) P.flagged[o] = 1;
+              s_q[qn * 256 + tid] = j | (cb << 24);
+              qn += 1;
             }
-          } while (fm);
+          }
         }
+      // a lane with a full queue forces a batch for the whole wave
+      if (__ballot(qn >= kQueue - 2 * NB * 2)) flush_queue();
     }
     if (t + 1 < ntile) store_tile(t + 1, buf ^ 1);
     __syncthreads();
   }
 
-  // ---- merge the two lanes that share a point, choose, refine ------------
+  flush_queue();
+
+  // ---- index of the best kept pair, merge the two lanes that share a
+  // point, choose between kept and corrected, refine in FP64 --------------
   double sse = 0.0;
   if constexpr (MODE == 0) {
 #pragma unroll
     for (int cb = 0; cb < NB; ++cb) {
+      // first register of the saved block holding the best value
+      int rs = 16;
+#pragma unroll
+      for (int r = 15; r >= 0; --r) rs = (sv[cb][r] == bw[cb]) ? r : rs;
+      int bj = (bb[cb] >= 0 && rs < 16) ? bb[cb] + acc_row(rs, lane) : -1;
       float ow = __shfl_xor(bw[cb], 32, kWave);
-      int oj = __shfl_xor(bj[cb], 32, kWave);
-      if (ow > bw[cb] || (ow == bw[cb] && oj >= 0 && (bj[cb] < 0 || oj < bj[cb]))) {
+      int oj = __shfl_xor(bj, 32, kWave);
+      if (ow > bw[cb] || (ow == bw[cb] && oj >= 0 && (bj < 0 || oj < bj))) {
         bw[cb] = ow;
-        bj[cb] = oj;
+        bj = oj;
       }
       float od = __shfl_xor(cd[cb], 32, kWave);
       int ojc = __shfl_xor(cj[cb], 32, kWave);
@@ -370,14 +462,15 @@ k_assign_mfma(const AssignProb* __restrict__ probs, const int32_t* __restrict__ 
         cd[cb] = od;
         cj[cb] = ojc;
       }
+      bb[cb] = bj;  // now the best kept centre index
     }
 #pragma unroll
     for (int cb = 0; cb < NB; ++cb) {
       if ((cb & 1) != (lane >> 5)) continue;  // lane half cb%2 finishes block cb
       const int pl = pw + cb * 32 + (lane & 31);
       if (pl >= nvalid) continue;
-      const float dk = bj[cb] >= 0 ? __builtin_fmaxf(nx[cb] - 2.0f * bw[cb], 0.0f) : __builtin_inff();
-      int lab = bj[cb];
+      const float dk = bb[cb] >= 0 ? __builtin_fmaxf(nx[cb] - 2.0f * bw[cb], 0.0f) : __builtin_inff();
+      int lab = bb[cb];
       if (cj[cb] >= 0 && (cd[cb] < dk || (cd[cb] == dk && cj[cb] < lab) || lab < 0)) lab = cj[cb];
       if (lab < 0 || lab >= P.k) lab = 0;  // only with non-finite data (status raised)
       const int64_t p = p0 + pl;
@@ -403,6 +496,373 @@ k_assign_mfma(const AssignProb* __restrict__ probs, const int32_t* __restrict__ 
       c += s_corr[w];
     }
     P.sse_part[tile] = s;
+    P.corr_part[tile] = c;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Fused mixed-precision assignment, software-pipelined (assignment mode).
+//
+// Same arithmetic as k_assign_mfma in assignment mode; the difference is the
+// schedule.  The sweep over 32-centre blocks keeps two accumulator sets: the
+// MFMAs of block b+1 are issued and, while the matrix core executes them, the
+// wave runs the epilogue of block b (sched_group_barrier interleaves one
+// MFMA with a few VALU instructions).  The saved copy of a lane's best block
+// lives in LDS and is written only when the lane's best value improves.
+// ---------------------------------------------------------------------------
+template <class L, int DP, int NB, bool FALLBACK>
+__global__ void __launch_bounds__(256, 2)
+k_assign_pipe(const AssignProb* __restrict__ probs, const int32_t* __restrict__ wg_start, int nprob) {
+  using Cfg = AssignCfg<L, DP, NB>;
+  using S = typename L::S;
+  constexpr int LD = Cfg::kLd;
+  constexpr int CT = Cfg::kCt;
+  constexpr int kQueue = 8;
+
+  __shared__ __attribute__((aligned(16))) unsigned char smem[Cfg::kBytes];
+  __shared__ float s_cinit[2][CT];
+  __shared__ float s_ca[3][CT];
+  __shared__ f32x4 s_sv[4][NB][4][64];  // saved best block: [wave][cb][r/4][lane]
+  __shared__ int s_q[FALLBACK ? kQueue * 256 : 1];
+  __shared__ double s_sse[Cfg::kWaves];
+  __shared__ unsigned long long s_corr[Cfg::kWaves];
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int pi = find_problem(wg_start, nprob, blockIdx.x);
+  const AssignProb& P = probs[pi];
+  const int tile = blockIdx.x - wg_start[pi];
+  const int64_t p0 = (int64_t)tile * Cfg::kPts;
+  const int64_t n = P.n;
+  const int d = P.d;
+  const int nvalid = (int)((n - p0) < Cfg::kPts ? (n - p0) : Cfg::kPts);
+
+  // ---- prologue: point fragments (RNE low precision) and quantised norms
+  typename L::frag bfr[NB][Cfg::kSteps];
+  float nx[NB], hx[NB];
+  const int pw = wave * NB * 32;
+  int bad = 0;
+  const bool vec4 = ((d & 3) == 0) && ((((uintptr_t)P.X) & 15) == 0);
+  const bool fast = vec4 && d == DP && nvalid == Cfg::kPts;
+#pragma unroll
+  for (int cb = 0; cb < NB; ++cb) {
+    const int pl = pw + cb * 32 + (lane & 31);
+    const bool pv = pl < nvalid;
+    const float* xr = P.X + (p0 + (pv ? pl : 0)) * d;
+    float part = 0.0f;
+#pragma unroll
+    for (int s = 0; s < Cfg::kSteps; ++s) {
+      const int o = s * L::KS + (lane >> 5) * L::KV;
+      float v[L::KV];
+      if constexpr (L::KV % 4 == 0) {
+        if (fast) {
+#pragma unroll
+          for (int u = 0; u < L::KV; u += 4) {
+            const f32x4 q = __builtin_nontemporal_load(reinterpret_cast<const f32x4*>(xr + o + u));
+            v[u] = q[0]; v[u + 1] = q[1]; v[u + 2] = q[2]; v[u + 3] = q[3];
+          }
+        } else {
+#pragma unroll
+          for (int u = 0; u < L::KV; ++u) v[u] = (pv && o + u < d) ? xr[o + u] : 0.0f;
+        }
+      } else {
+#pragma unroll
+        for (int u = 0; u < L::KV; ++u) v[u] = (pv && o + u < d) ? xr[o + u] : 0.0f;
+      }
+      typename L::frag f;
+#pragma unroll
+      for (int u = 0; u < L::KV; ++u) {
+        if (!__builtin_isfinite(v[u])) bad |= kStatusNonFinite;
+        if (L::kHasRange && __builtin_fabsf(v[u]) >= L::kOverflow) bad |= kStatusRange;
+        const S q = L::cvt(v[u]);
+        if constexpr (L::KV == 1) f = q; else f[u] = q;
+        const float qf = L::tof(q);
+        part = __builtin_fmaf(qf, qf, part);
+      }
+      bfr[cb][s] = f;
+    }
+    const float other = __shfl_xor(part, 32, kWave);
+    nx[cb] = (lane < 32) ? part + other : other + part;
+    hx[cb] = pv ? 0.5f * (P.oma * nx[cb]) : __builtin_inff();
+  }
+  raise_status(P.status, bad);
+
+  S* const sc0 = reinterpret_cast<S*>(smem);
+  float bw[NB];
+  int bb[NB];
+  float cd[NB];
+  int cj[NB];
+#pragma unroll
+  for (int cb = 0; cb < NB; ++cb) {
+    bw[cb] = -__builtin_inff();
+    bb[cb] = -1;
+    cd[cb] = __builtin_inff();
+    cj[cb] = -1;
+  }
+  unsigned long long ncorr = 0;
+  int qn = 0;
+  auto flush_queue = [&]() {
+    if constexpr (FALLBACK) {
+      for (int q = 0; q < qn; ++q) {
+        const int e = s_q[q * 256 + tid];
+        const int j = e & 0xffffff;
+        const int cbq = e >> 24;
+        const int pl = pw + cbq * 32 + (lane & 31);
+        const double dd = sqdist64_call(P.X + (p0 + pl) * d, P.C + (int64_t)j * d, d);
+        const float df = (float)dd;
+        ncorr += 1;
+#pragma unroll
+        for (int cb = 0; cb < NB; ++cb) {
+          if (cb != cbq) continue;
+          if (df < cd[cb] || (df == cd[cb] && j < cj[cb])) {
+            cd[cb] = df;
+            cj[cb] = j;
+          }
+        }
+      }
+      qn = 0;
+    }
+  };
+
+  const int kpad = P.k_pad;
+  const int ntile = (kpad + CT - 1) / CT;
+  const S* Cq = reinterpret_cast<const S*>(P.Cq);
+  f32x4 stage[Cfg::kChunksPerThread];
+  float st_ci = 0.f, st_ca = 0.f;
+  auto load_tile = [&](int t) {
+    const int rows = (kpad - t * CT) < CT ? (kpad - t * CT) : CT;
+    const f32x4* g = reinterpret_cast<const f32x4*>(Cq + (int64_t)t * CT * DP);
+    const int nchunk = rows * DP / Cfg::kElemsPerChunk;
+#pragma unroll
+    for (int u = 0; u < Cfg::kChunksPerThread; ++u) {
+      const int c = tid + u * 256;
+      if (c < nchunk) stage[u] = g[c];
+    }
+    if (tid < rows) {
+      st_ci = P.cinit[t * CT + tid];
+      st_ca = P.ca[t * CT + tid];
+    }
+  };
+  auto store_tile = [&](int t) {
+    const int rows = (kpad - t * CT) < CT ? (kpad - t * CT) : CT;
+    const int nchunk = rows * DP / Cfg::kElemsPerChunk;
+    constexpr int CPR = DP / Cfg::kElemsPerChunk;
+    S* dst = sc0 + (t & 1) * CT * LD;
+#pragma unroll
+    for (int u = 0; u < Cfg::kChunksPerThread; ++u) {
+      const int c = tid + u * 256;
+      if (c < nchunk) {
+        const int row = c / CPR, col = (c % CPR) * Cfg::kElemsPerChunk;
+        *reinterpret_cast<f32x4*>(dst + row * LD + col) = stage[u];
+      }
+    }
+    if (tid < rows) {
+      s_cinit[t & 1][tid] = st_ci;
+      s_ca[t % 3][tid] = st_ca;
+    }
+  };
+
+  // MFMAs of one 32-centre block: acc = -nc/2 + x~^T c~
+  auto issue = [&](f32x16 (&acc)[NB], int t, int bk) {
+    const S* arow = sc0 + (t & 1) * CT * LD + (bk * 32 + (lane & 31)) * LD + (lane >> 5) * L::KV;
+    typename L::frag af[Cfg::kSteps];
+#pragma unroll
+    for (int s = 0; s < Cfg::kSteps; ++s) {
+      if constexpr (L::KV == 1) af[s] = arow[s * L::KS];
+      else af[s] = *reinterpret_cast<const typename L::frag*>(arow + s * L::KS);
+    }
+    f32x16 ci;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) ci[r] = s_cinit[t & 1][bk * 32 + acc_row(r, lane)];
+#pragma unroll
+    for (int cb = 0; cb < NB; ++cb) acc[cb] = L::mfma(af[0], bfr[cb][0], ci);
+#pragma unroll
+    for (int s = 1; s < Cfg::kSteps; ++s)
+#pragma unroll
+      for (int cb = 0; cb < NB; ++cb) acc[cb] = L::mfma(af[s], bfr[cb][s], acc[cb]);
+  };
+  // epilogue part 1 (overlaps the next block's MFMAs): block maxima of the
+  // test quantity W + ca and of W
+  auto epi1 = [&](const f32x16 (&acc)[NB], int t, int bk, float (&tm)[NB], float (&wm)[NB]) {
+    if constexpr (FALLBACK) {
+      f32x16 cav;
+#pragma unroll
+      for (int r = 0; r < 16; ++r) cav[r] = s_ca[t % 3][bk * 32 + acc_row(r, lane)];
+#pragma unroll
+      for (int cb = 0; cb < NB; ++cb) tm[cb] = max16(acc[cb] + cav);
+    }
+#pragma unroll
+    for (int cb = 0; cb < NB; ++cb) wm[cb] = max16(acc[cb]);
+  };
+  // epilogue part 2: rare slow path for flagged pairs, then the running best
+  auto epi2 = [&](const f32x16 (&acc)[NB], int t, int bk, float (&tm)[NB], float (&wm)[NB]) {
+    const int jb = t * CT + bk * 32;
+#pragma unroll
+    for (int cb = 0; cb < NB; ++cb) {
+      f32x16 w = acc[cb];
+      if constexpr (FALLBACK) {
+        if (__builtin_expect(__ballot(tm[cb] >= hx[cb]) != 0, 0)) {  // rare, wave-uniform
+          const int pl = pw + cb * 32 + (lane & 31);
+          uint32_t fm = 0;
+#pragma unroll
+          for (int r = 0; r < 16; ++r) {
+            const bool f = w[r] + s_ca[t % 3][bk * 32 + acc_row(r, lane)] >= hx[cb];
+            fm |= (uint32_t)f << r;
+            w[r] = f ? -__builtin_inff() : w[r];
+          }
+          wm[cb] = max16(w);
+          if (pl >= nvalid) fm = 0;
+          while (fm) {
+            const int r = __builtin_ctz(fm);
+            fm &= fm - 1;
+            const int j = jb + acc_row(r, lane);
+            if (j >= P.k) continue;
+            if (qn < kQueue) {
+              s_q[qn * 256 + tid] = j | (cb << 24);
+              qn += 1;
+            } else {  // queue full (dense flags): correct this pair now
+              const float df = (float)sqdist64_call(P.X + (p0 + pl) * d, P.C + (int64_t)j * d, d);
+              ncorr += 1;
+              if (df < cd[cb] || (df == cd[cb] && j < cj[cb])) {
+                cd[cb] = df;
+                cj[cb] = j;
+              }
+            }
+          }
+        }
+      }
+      if (wm[cb] > bw[cb]) {  // strict: the earlier block keeps ties
+        bw[cb] = wm[cb];
+        bb[cb] = jb;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          f32x4 v = {w[4 * q], w[4 * q + 1], w[4 * q + 2], w[4 * q + 3]};
+          s_sv[wave][cb][q][lane] = v;
+        }
+      }
+    }
+  };
+
+  load_tile(0);
+  store_tile(0);
+  __syncthreads();
+
+  f32x16 accA[NB], accB[NB];
+  float tm[NB], wm[NB];
+  // one region: MFMAs of the next block interleaved with the epilogue
+  // (block maxima) of the previous one
+#define KM_INTERLEAVE()                                        \
+  _Pragma("unroll") for (int i_ = 0; i_ < Cfg::kSteps * NB; ++i_) { \
+    __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);         \
+    __builtin_amdgcn_sched_group_barrier(0x002, 4, 0);         \
+  }
+  // tile 0
+  const int nbk0 = (kpad < CT ? kpad : CT) / 32;
+  if (1 < ntile) load_tile(1);
+  issue(accA, 0, 0);
+  if (nbk0 == 2) {
+    issue(accB, 0, 1);
+    epi1(accA, 0, 0, tm, wm);
+    KM_INTERLEAVE();
+    epi2(accA, 0, 0, tm, wm);
+  }
+  if (1 < ntile) store_tile(1);
+  __syncthreads();
+  // tiles 1..: every tile before the last holds two blocks
+  for (int t = 1; t < ntile; ++t) {
+    if (t + 1 < ntile) load_tile(t + 1);
+    issue(accA, t, 0);
+    epi1(accB, t - 1, 1, tm, wm);
+    KM_INTERLEAVE();
+    epi2(accB, t - 1, 1, tm, wm);
+    const int nbk = ((kpad - t * CT) < CT ? (kpad - t * CT) : CT) / 32;
+    if (nbk == 2) {
+      issue(accB, t, 1);
+      epi1(accA, t, 0, tm, wm);
+      KM_INTERLEAVE();
+      epi2(accA, t, 0, tm, wm);
+    }
+    if (t + 1 < ntile) store_tile(t + 1);
+    if constexpr (FALLBACK) {
+      if (__ballot(qn >= kQueue / 2)) flush_queue();  // batch: rare flags wait to the end
+    }
+    __syncthreads();
+  }
+#undef KM_INTERLEAVE
+  {
+    const int tl = ntile - 1;
+    const int nbkl = ((kpad - tl * CT) < CT ? (kpad - tl * CT) : CT) / 32;
+    if (nbkl == 2) {
+      epi1(accB, tl, 1, tm, wm);
+      epi2(accB, tl, 1, tm, wm);
+    } else {
+      epi1(accA, tl, 0, tm, wm);
+      epi2(accA, tl, 0, tm, wm);
+    }
+  }
+  flush_queue();
+
+  // ---- index of the best kept pair, merge the two lanes that share a
+  // point, choose between kept and corrected, refine in FP64
+  double sse = 0.0;
+#pragma unroll
+  for (int cb = 0; cb < NB; ++cb) {
+    int rs = 16;
+    if (bb[cb] >= 0) {
+#pragma unroll
+      for (int q = 3; q >= 0; --q) {
+        const f32x4 v = s_sv[wave][cb][q][lane];
+#pragma unroll
+        for (int e = 3; e >= 0; --e) rs = (v[e] == bw[cb]) ? 4 * q + e : rs;
+      }
+    }
+    int bj = (bb[cb] >= 0 && rs < 16) ? bb[cb] + acc_row(rs, lane) : -1;
+    float ow = __shfl_xor(bw[cb], 32, kWave);
+    int oj = __shfl_xor(bj, 32, kWave);
+    if (ow > bw[cb] || (ow == bw[cb] && oj >= 0 && (bj < 0 || oj < bj))) {
+      bw[cb] = ow;
+      bj = oj;
+    }
+    float od = __shfl_xor(cd[cb], 32, kWave);
+    int ojc = __shfl_xor(cj[cb], 32, kWave);
+    if (od < cd[cb] || (od == cd[cb] && ojc >= 0 && (cj[cb] < 0 || ojc < cj[cb]))) {
+      cd[cb] = od;
+      cj[cb] = ojc;
+    }
+    bb[cb] = bj;
+  }
+#pragma unroll
+  for (int cb = 0; cb < NB; ++cb) {
+    if ((cb & 1) != (lane >> 5)) continue;
+    const int pl = pw + cb * 32 + (lane & 31);
+    if (pl >= nvalid) continue;
+    const float dk = bb[cb] >= 0 ? __builtin_fmaxf(nx[cb] - 2.0f * bw[cb], 0.0f) : __builtin_inff();
+    int lab = bb[cb];
+    if (cj[cb] >= 0 && (cd[cb] < dk || (cd[cb] == dk && cj[cb] < lab) || lab < 0)) lab = cj[cb];
+    if (lab < 0 || lab >= P.k) lab = 0;  // only with non-finite data (status raised)
+    const int64_t p = p0 + pl;
+    const double dd = sqdist64_call(P.X + p * d, P.C + (int64_t)lab * d, d);
+    P.labels[p] = lab;
+    if (P.mindist) P.mindist[p] = (float)dd;
+    sse += dd;
+  }
+  sse = wave_sum(sse);
+  unsigned long long nc = wave_sum_u64(ncorr);
+  if (lane == 0) {
+    s_sse[wave] = sse;
+    s_corr[wave] = nc;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    double ssum = 0.0;
+    unsigned long long c = 0;
+#pragma unroll
+    for (int w = 0; w < Cfg::kWaves; ++w) {
+      ssum += s_sse[w];
+      c += s_corr[w];
+    }
+    P.sse_part[tile] = ssum;
     P.corr_part[tile] = c;
   }
 }
@@ -613,9 +1073,9 @@ static hipError_t launch_mfma_t(int mode, bool fallback, const AssignProb* dprob
                                 int nprob, int nwg, hipStream_t st) {
   if (mode == 0) {
     if (fallback)
-      hipLaunchKernelGGL((k_assign_mfma<L, DP, NB, 0, true>), dim3(nwg), dim3(256), 0, st, dprobs, dstart, nprob);
+      hipLaunchKernelGGL((k_assign_pipe<L, DP, NB, true>), dim3(nwg), dim3(256), 0, st, dprobs, dstart, nprob);
     else
-      hipLaunchKernelGGL((k_assign_mfma<L, DP, NB, 0, false>), dim3(nwg), dim3(256), 0, st, dprobs, dstart, nprob);
+      hipLaunchKernelGGL((k_assign_pipe<L, DP, NB, false>), dim3(nwg), dim3(256), 0, st, dprobs, dstart, nprob);
   } else {
     if (fallback)
       hipLaunchKernelGGL((k_assign_mfma<L, DP, NB, 1, true>), dim3(nwg), dim3(256), 0, st, dprobs, dstart, nprob);

@@ -106,6 +106,10 @@ __device__ inline double sqdist64(const float* __restrict__ x,
   return s;
 }
 
+// Out-of-line copy for rare paths (keeps the hot loops compact).
+__device__ __noinline__ double sqdist64_call(const float* __restrict__ x,
+                                            const float* __restrict__ c, int d);
+
 // Wavefront sum of a double in a fixed butterfly order (deterministic).
 __device__ inline double wave_sum(double v) {
 #pragma unroll

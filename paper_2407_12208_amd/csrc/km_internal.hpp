@@ -27,8 +27,7 @@ constexpr int padded_dim(int d) {
 // 32-point column blocks per wave (the point fragments of all of them stay in
 // registers for the whole sweep over the centres).
 constexpr int mfma_nb(int low, int DP) {
-  return low == kLowFP32 ? (DP <= 32 ? 2 : 1)
-                         : (DP <= 32 ? 4 : DP <= 128 ? 2 : 1);
+  return low == kLowFP32 ? (DP <= 32 ? 2 : 1) : (DP <= 128 ? 2 : 1);
 }
 constexpr int mfma_points_per_wg(int low, int DP) { return 4 * 32 * mfma_nb(low, DP); }
 constexpr int kDirectPointsPerWg = 64;

@@ -13,7 +13,8 @@
 //   4. scatter   stable counting sort of point indices by label: members of
 //                a cluster appear in ascending point order;
 //   5. chunksum  one wave per chunk of <= 256 consecutive members of one
-//                cluster, lanes over coordinates, sequential FP64 sums;
+//                cluster: FP64 sums over fixed member groups, combined by a
+//                fixed butterfly;
 //   6. finalize  per cluster, sum of its chunk partials in order, division,
 //                one rounding to FP32, empty clusters keep their centre,
 //                squared move;
@@ -138,28 +139,65 @@ k_upd_scan_cl(const UpdateProb* __restrict__ probs) {
   }
 }
 
-// 4. stable scatter of point indices into cluster order
+// 4. stable scatter of point indices into cluster order.  One wave per
+// 1024-point tile walks the tile in 16 rounds of 64 points; inside a round
+// the lanes holding one label are found with a ballot loop (one iteration per
+// distinct label), ranked by lane order, and placed after the earlier rounds'
+// points of that label (per-wave counters in LDS).  Members of a cluster thus
+// appear in ascending point order.  k > kScatterLds uses the brute-force rank.
+constexpr int kScatterLds = 4096;
+
 __global__ void __launch_bounds__(256)
 k_upd_scatter(const UpdateProb* __restrict__ probs, const int32_t* __restrict__ wg_start, int nprob) {
-  __shared__ int lab_s[kUpdTile];
+  __shared__ int cnt[4][kScatterLds];
   const int pi = find_prob(wg_start, nprob, blockIdx.x);
   const UpdateProb& P = probs[pi];
-  const int tile = blockIdx.x - wg_start[pi];
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int tile = (blockIdx.x - wg_start[pi]) * 4 + wave;
+  if (tile >= P.ntiles) return;
   const int64_t p0 = (int64_t)tile * kUpdTile;
   const int m = (int)((P.n - p0) < kUpdTile ? (P.n - p0) : kUpdTile);
-  for (int i = threadIdx.x; i < m; i += 256) lab_s[i] = P.labels[p0 + i];
-  __syncthreads();
-  for (int i = threadIdx.x; i < m; i += 256) {
-    const int lab = lab_s[i];
-    if (lab < 0 || lab >= P.k) continue;
-    int rank = 0;
-    for (int q = 0; q < i; ++q) rank += (lab_s[q] == lab);
-    const int pos = P.cstart[lab] + P.offs[(int64_t)lab * P.ntiles + tile] + rank;
-    P.perm[pos] = (int32_t)(p0 + i);
+  if (P.k <= kScatterLds) {
+    int* c = cnt[wave];
+    // running output position of each cluster for this tile
+    for (int j = lane; j < P.k; j += 64) c[j] = P.cstart[j] + P.offs[(int64_t)j * P.ntiles + tile];
+    const unsigned long long below = (1ull << lane) - 1;
+    for (int r0 = 0; r0 < m; r0 += 64) {
+      const int i = r0 + lane;
+      const int lab = i < m ? P.labels[p0 + i] : -1;
+      const bool ok = lab >= 0 && lab < P.k;
+      unsigned long long todo = __ballot(ok);
+      while (todo) {
+        const int leader = __ffsll((long long)todo) - 1;
+        const int L = __shfl(lab, leader, kWave);
+        const unsigned long long grp = __ballot(ok && lab == L);
+        if (ok && lab == L) {
+          const int rank = __popcll(grp & below);
+          P.perm[c[L] + rank] = (int32_t)(p0 + i);
+        }
+        // every lane of the group has read c[L] above before the leader
+        // writes it (the wave executes the read before the write)
+        if (lane == leader) c[L] += __popcll(grp);
+        todo &= ~grp;
+      }
+    }
+  } else {
+    for (int i = lane; i < m; i += 64) {
+      const int lab = P.labels[p0 + i];
+      if (lab < 0 || lab >= P.k) continue;
+      int rank = 0;
+      for (int q = 0; q < i; ++q) rank += (P.labels[p0 + q] == lab);
+      const int pos = P.cstart[lab] + P.offs[(int64_t)lab * P.ntiles + tile] + rank;
+      P.perm[pos] = (int32_t)(p0 + i);
+    }
   }
 }
 
-// 5. one wave per chunk of <= 256 members of a cluster; lanes over coordinates
+// 5. one wave per chunk of <= 256 members of one cluster.  Lanes are split
+// into G member groups x DPW coordinate slots (DPW = next power of two >= d
+// when d <= 64, else 64 with several coordinates per lane); each lane sums its
+// group's members (every G-th member, ascending) in FP64, then the groups are
+// combined by a fixed butterfly.  The order depends only on the chunk.
 __global__ void __launch_bounds__(256)
 k_upd_chunksum(const UpdateProb* __restrict__ probs, const int32_t* __restrict__ wg_start, int nprob) {
   const int pi = find_prob(wg_start, nprob, blockIdx.x);
@@ -177,12 +215,51 @@ k_upd_chunksum(const UpdateProb* __restrict__ probs, const int32_t* __restrict__
   const int m0 = P.cstart[j] + (c - P.chunk_start[j]) * kUpdChunk;
   const int m1 = (m0 + kUpdChunk) < P.cstart[j + 1] ? (m0 + kUpdChunk) : P.cstart[j + 1];
   const int d = P.d;
-  for (int l0 = 0; l0 < d; l0 += 64) {
-    const int l = l0 + lane;
-    double s = 0.0;
-    if (l < d) {
-      for (int mm = m0; mm < m1; ++mm) s += (double)P.X[(int64_t)P.perm[mm] * d + l];
-      P.chunk_sum[(int64_t)c * d + l] = s;
+  int dpw = 1;
+  while (dpw < d && dpw < 64) dpw <<= 1;
+  const int G = 64 / dpw;            // member groups
+  const int g = lane / dpw, cl = lane % dpw;
+  constexpr int kMaxSlots = 4;       // d <= 256
+  const int nslot = (d + 63) / 64;   // coordinates per lane when d > 64
+  double s[kMaxSlots] = {0.0, 0.0, 0.0, 0.0};
+  const float* __restrict__ X = P.X;
+  int mm = m0 + g;
+  // 8 members per batch of independent loads
+  for (; mm + 7 * G < m1; mm += 8 * G) {
+    int idx[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) idx[u] = P.perm[mm + u * G];
+#pragma unroll
+    for (int q = 0; q < kMaxSlots; ++q) {
+      if (q >= nslot) break;
+      const int l = cl + 64 * q;
+      float v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) v[u] = (l < d) ? X[(int64_t)idx[u] * d + l] : 0.0f;
+#pragma unroll
+      for (int u = 0; u < 8; ++u) s[q] += (double)v[u];
+    }
+  }
+  for (; mm < m1; mm += G) {
+    const int id = P.perm[mm];
+#pragma unroll
+    for (int q = 0; q < kMaxSlots; ++q) {
+      if (q >= nslot) break;
+      const int l = cl + 64 * q;
+      if (l < d) s[q] += (double)X[(int64_t)id * d + l];
+    }
+  }
+  // combine the G groups (fixed butterfly over the group bits)
+  for (int o = dpw; o < 64; o <<= 1) {
+#pragma unroll
+    for (int q = 0; q < kMaxSlots; ++q) s[q] += __shfl_xor(s[q], o, kWave);
+  }
+  if (g == 0) {
+#pragma unroll
+    for (int q = 0; q < kMaxSlots; ++q) {
+      if (q >= nslot) break;
+      const int l = cl + 64 * q;
+      if (l < d) P.chunk_sum[(int64_t)c * d + l] = s[q];
     }
   }
 }
@@ -245,9 +322,10 @@ k_upd_shift(const UpdateProb* __restrict__ probs) {
 // cluster prefix, then chunk-wave prefix and cluster-wave prefix.
 hipError_t launch_update(const UpdateProb* dprobs, const UpdateProb* hprobs, int nprob,
                          const int32_t* dpre, hipStream_t st) {
-  int tiles = 0, clusters = 0, chunkwg = 0, clwg = 0;
+  int tiles = 0, clusters = 0, chunkwg = 0, clwg = 0, scatwg = 0;
   for (int i = 0; i < nprob; ++i) {
     tiles += hprobs[i].ntiles;
+    scatwg += (hprobs[i].ntiles + 3) / 4;
     clusters += hprobs[i].k;
     chunkwg += (int)((hprobs[i].n + kUpdChunk - 1) / kUpdChunk + hprobs[i].k + 3) / 4;
     clwg += (hprobs[i].k + 3) / 4;
@@ -256,10 +334,11 @@ hipError_t launch_update(const UpdateProb* dprobs, const UpdateProb* hprobs, int
   const int32_t* pre_cl = dpre + (nprob + 1);
   const int32_t* pre_chunk = dpre + 2 * (nprob + 1);
   const int32_t* pre_clwg = dpre + 3 * (nprob + 1);
+  const int32_t* pre_scat = dpre + 4 * (nprob + 1);
   if (tiles > 0) hipLaunchKernelGGL(k_upd_hist, dim3(tiles), dim3(256), 0, st, dprobs, pre_tiles, nprob);
   hipLaunchKernelGGL(k_upd_scan_rel, dim3(clusters), dim3(256), 0, st, dprobs, pre_cl, nprob);
   hipLaunchKernelGGL(k_upd_scan_cl, dim3(nprob), dim3(1024), 0, st, dprobs);
-  if (tiles > 0) hipLaunchKernelGGL(k_upd_scatter, dim3(tiles), dim3(256), 0, st, dprobs, pre_tiles, nprob);
+  if (tiles > 0) hipLaunchKernelGGL(k_upd_scatter, dim3(scatwg), dim3(256), 0, st, dprobs, pre_scat, nprob);
   if (chunkwg > 0) hipLaunchKernelGGL(k_upd_chunksum, dim3(chunkwg), dim3(256), 0, st, dprobs, pre_chunk, nprob);
   hipLaunchKernelGGL(k_upd_finalize, dim3(clwg), dim3(256), 0, st, dprobs, pre_clwg, nprob);
   hipLaunchKernelGGL(k_upd_shift, dim3(nprob), dim3(256), 0, st, dprobs);

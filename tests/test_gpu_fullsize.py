@@ -92,5 +92,6 @@ def test_large_clustering_full_assign(ctx):
         labels, mind, _, st = km.kmeans_assign(ctx, Xd, torch.from_numpy(C0).cuda(), p, mindist=True)
         # at random initial centres several centres share a blob: more near
         # ties than at convergence, so the gate covers fewer points
+        # (the FP32 bound is the worst case of thm:dist-exp and covers fewer)
         check_assignment(X, C0, fmt, st["alpha_used"], host(labels), host(mind), None, None,
-                         min_coverage=0.95, rows=rows)
+                         min_coverage=0.95 if fmt < 2 else 0.85, rows=rows)
