@@ -35,6 +35,64 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+def serve_run(km, ctx, reqs, arrivals, max_active, budget):
+    """Submit requests at their arrival times to a server; return per-request
+    latency (submit -> done) and the wall time from first arrival to last
+    completion."""
+    srv = km.Server(ctx, budget, max_active=max_active)
+    n = len(reqs)
+    t0 = time.perf_counter()
+    tickets, t_sub, t_done = [None] * n, [0.0] * n, [None] * n
+    nxt, left = 0, n
+    while left:
+        now = time.perf_counter() - t0
+        while nxt < n and arrivals[nxt] <= now:
+            r = reqs[nxt]
+            t_sub[nxt] = time.perf_counter() - t0
+            tickets[nxt] = srv.submit(r.X, r.C0, r.iters)
+            nxt += 1
+        for i in range(nxt):
+            if t_done[i] is None:
+                rc = srv.poll(tickets[i], 0)
+                if rc != 1:
+                    if rc != 0:
+                        raise RuntimeError("served request %d failed: %d" % (i, rc))
+                    t_done[i] = time.perf_counter() - t0
+                    left -= 1
+        time.sleep(0.0002)
+    srv.close()
+    lat = [t_done[i] - t_sub[i] for i in range(n)]
+    return lat, max(t_done) - min(t_sub)
+
+
+def serve_bench(km, ctx, count, seed):
+    """Continuous batching vs one solve at a time on Poisson arrivals of
+    k-means requests (n log-uniform in [1e3, 1e6], d in {3,16,64,128}, k in
+    {8..512}, 30 rounds each).  The arrival rate equals the measured
+    one-at-a-time capacity."""
+    import numpy as np
+    import workloads as W
+    reqs = [r.materialize() for r in W.request_stream(count, 1.0, seed)]
+    budget = 64 << 30
+    # one-at-a-time capacity: back-to-back solves through a single-slot server
+    lat1, wall1 = serve_run(km, ctx, reqs, [0.0] * count, 1, budget)
+    mu1 = count / wall1
+    g = np.random.default_rng(seed + 1)
+    arrivals = np.cumsum(g.exponential(1.0 / mu1, size=count))
+    arrivals -= arrivals[0]
+    out = {"requests": count, "one_at_a_time_capacity_per_s": mu1}
+    for load in (1.0, 1.5):
+        arr = list(arrivals / load)
+        res = {"arrival_rate_per_s": mu1 * load}
+        for name, slots in (("one_at_a_time", 1), ("continuous_batching", 64)):
+            lat, wall = serve_run(km, ctx, reqs, arr, slots, budget)
+            res[name] = {"solves_per_s": count / wall,
+                         "p50_latency_ms": 1e3 * float(np.percentile(lat, 50)),
+                         "p99_latency_ms": 1e3 * float(np.percentile(lat, 99))}
+        out["load_%.1f" % load] = res
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -43,6 +101,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-extra", action="store_true", help="skip the extra measurements")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--serve-requests", type=int, default=48,
+                    help="requests in the serving measurement (0 = skip)")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="also run a plain device copy of this size (counter calibration)")
     args = ap.parse_args()
@@ -118,7 +178,7 @@ def main():
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": MFMA_FP16_PEAK_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / MFMA_FP16_PEAK_TFLOPS,
                      "traffic": None,
-                     "kernel": "k_assign_mfma<LowF16,128,2,0,true>",
+                     "kernel": "k_assign_pipe<LowF16,128,2,true>",
                      "kernel_avg_ms": kern_avg_ms,
                      "algorithmic_flops_per_launch": flops},
     }
@@ -162,6 +222,8 @@ def main():
             res[name] = cs["iters"] / dt
         extra["lloyd_small_iters_per_s"] = res["mixed_fp16_fp64"]
         extra["lloyd_small_iters_per_s_fp64_direct"] = res["fp64_direct"]
+        if args.serve_requests > 0:
+            extra["serving"] = serve_bench(km, ctx, args.serve_requests, 3005)
         out["extra"] = extra
         log("extra: %s" % json.dumps(extra))
 

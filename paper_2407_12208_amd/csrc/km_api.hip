@@ -357,7 +357,7 @@ int32_t kmeans_context_destroy(km_context* c) {
 
 namespace km {
 
-static int32_t check_shape(int64_t n, int32_t d, int32_t k, const km_precision& p) {
+int32_t check_shape(int64_t n, int32_t d, int32_t k, const km_precision& p) {
   if (n < 1 || n > (int64_t)INT32_MAX - 1024 || d < 1 || k < 1 || k > 65536) return KM_ERR_ARG;
   if (p.low != KM_EXACT64) {
     const int DP = padded_dim(d);
@@ -367,18 +367,7 @@ static int32_t check_shape(int64_t n, int32_t d, int32_t k, const km_precision& 
   return KM_OK;
 }
 
-// Everything one assignment pass of one problem needs on the device.
-struct PassBufs {
-  void* Cq;
-  float* cinit;
-  float* ca;
-  double* sse_part;
-  unsigned long long* corr_part;
-  int* status;
-  KResult* result;
-};
-
-static void plan_pass(Plan& pl, const AssignPlan& a) {
+void plan_pass(Plan& pl, const AssignPlan& a) {
   pl.add<char>((size_t)a.k_pad * a.DP * 4);
   pl.add<float>(a.k_pad);
   pl.add<float>(a.k_pad);
@@ -388,7 +377,7 @@ static void plan_pass(Plan& pl, const AssignPlan& a) {
   pl.add<KResult>(1);
 }
 
-static PassBufs carve_pass(Arena& ar, const AssignPlan& a) {
+PassBufs carve_pass(Arena& ar, const AssignPlan& a) {
   PassBufs b;
   b.Cq = ar.take<char>((size_t)a.k_pad * a.DP * 4);
   b.cinit = ar.take<float>(a.k_pad);
@@ -400,7 +389,7 @@ static PassBufs carve_pass(Arena& ar, const AssignPlan& a) {
   return b;
 }
 
-static bool uses_prep(const AssignPlan& a) { return a.route == Route::Mfma || a.route == Route::MfmaNoFallback; }
+bool uses_prep(const AssignPlan& a) { return a.route == Route::Mfma || a.route == Route::MfmaNoFallback; }
 
 // Enqueue one assignment pass (prep + assign + reduce) of one problem.
 static hipError_t enqueue_pass(km_context_impl* ctx, const AssignPlan& a, const PassBufs& b,
@@ -628,20 +617,9 @@ int32_t kmeans_lloyd(km_context* ctx, const float* X, int64_t n, int32_t d, int3
 // ---------------------------------------------------------------------------
 namespace km {
 
-struct BatchState {
-  km_problem* prob;
-  AssignPlan plan;
-  PassBufs bufs;
-  UpdateProb upd;
-  float* cur;
-  float* nxt;
-  int32_t it = 0;
-  bool done = false;  // update rounds finished (converged or max_iter)
-};
-
 // Enqueue one assignment pass for every listed problem: one prep launch per
 // low format, one assignment launch per (route, DP) group, one reduce launch.
-static hipError_t enqueue_batch_pass(km_context_impl* ctx, std::vector<BatchState*>& list, bool final_pass,
+hipError_t enqueue_batch_pass(km_context_impl* ctx, std::vector<BatchState*>& list, bool final_pass,
                                      hipStream_t st) {
   if (list.empty()) return hipSuccess;
   // prep
@@ -721,6 +699,26 @@ static hipError_t enqueue_batch_pass(km_context_impl* ctx, std::vector<BatchStat
   return run_reduce(ctx, rp, st);
 }
 
+hipError_t enqueue_batch_round(km_context_impl* ctx, std::vector<BatchState*>& act, hipStream_t st) {
+  if (act.empty()) return hipSuccess;
+  hipError_t e = enqueue_batch_pass(ctx, act, false, st);
+  if (e != hipSuccess) return e;
+  std::vector<UpdateProb> up;
+  for (BatchState* s : act) {
+    s->upd.C_old = s->cur;
+    s->upd.C_new = s->nxt;
+    up.push_back(s->upd);
+  }
+  e = run_update(ctx, up, st);
+  if (e != hipSuccess) return e;
+  for (BatchState* s : act) {
+    std::swap(s->cur, s->nxt);
+    s->it += 1;
+    if (s->it >= s->prob->max_iter) s->done = true;
+  }
+  return hipSuccess;
+}
+
 }  // namespace km
 
 extern "C" int32_t kmeans_solve_batch(km_context* ctx, km_problem* probs, int32_t count,
@@ -773,19 +771,7 @@ extern "C" int32_t kmeans_solve_batch(km_context* ctx, km_problem* probs, int32_
     for (auto& s : S)
       if (!s.done) act.push_back(&s);
     if (act.empty()) break;
-    KM_HIP(enqueue_batch_pass(ctx, act, false, st));
-    std::vector<UpdateProb> up;
-    for (BatchState* s : act) {
-      s->upd.C_old = s->cur;
-      s->upd.C_new = s->nxt;
-      up.push_back(s->upd);
-    }
-    KM_HIP(run_update(ctx, up, st));
-    for (BatchState* s : act) {
-      std::swap(s->cur, s->nxt);
-      s->it += 1;
-      if (s->it >= s->prob->max_iter) s->done = true;
-    }
+    KM_HIP(enqueue_batch_round(ctx, act, st));
     if (need_tol) {
       for (size_t i = 0; i < act.size(); ++i)
         KM_HIP(hipMemcpyAsync(ctx->h_result + i, act[i]->bufs.result, sizeof(KResult), hipMemcpyDeviceToHost, st));

@@ -118,6 +118,38 @@ hipError_t run_update(km_context_impl* ctx, const std::vector<UpdateProb>& probs
 void plan_update(Plan& pl, int64_t n, int d, int k);
 UpdateProb carve_update(Arena& a, int64_t n, int d, int k);
 
+// Everything one assignment pass of one problem needs on the device.
+struct PassBufs {
+  void* Cq;
+  float* cinit;
+  float* ca;
+  double* sse_part;
+  unsigned long long* corr_part;
+  int* status;
+  KResult* result;
+};
+void plan_pass(Plan& pl, const AssignPlan& a);
+PassBufs carve_pass(Arena& ar, const AssignPlan& a);
+bool uses_prep(const AssignPlan& a);
+int32_t check_shape(int64_t n, int32_t d, int32_t k, const km_precision& p);
+
+// One problem inside a batched solve (device pointers in *prob).
+struct BatchState {
+  km_problem* prob;
+  AssignPlan plan;
+  PassBufs bufs;
+  UpdateProb upd;
+  float* cur;
+  float* nxt;
+  int32_t it = 0;
+  bool done = false;  // update rounds finished (converged or max_iter)
+};
+// One assignment pass for every listed problem (final = write mindist).
+hipError_t enqueue_batch_pass(km_context_impl* ctx, std::vector<BatchState*>& list, bool final_pass,
+                              hipStream_t st);
+// One Lloyd round (assignment pass + centre update) for every listed problem.
+hipError_t enqueue_batch_round(km_context_impl* ctx, std::vector<BatchState*>& act, hipStream_t st);
+
 }  // namespace km
 
 struct km_context : km::km_context_impl {};

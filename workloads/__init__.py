@@ -78,18 +78,12 @@ def blobs(n: int, d: int, k: int, seed: int, *, center_box=(-10.0, 10.0),
     sizes = np.full(k, n // k, dtype=np.int64)
     sizes[: n % k] += 1
     truth = np.repeat(np.arange(k, dtype=np.int32), sizes)
-    X = np.empty((n, d), dtype=np.float32)
-    # draw blob by blob in chunks so peak memory stays ~ one float64 copy
-    start = 0
-    for j in range(k):
-        m = int(sizes[j])
-        z = g.standard_normal(size=(m, d))
-        X[start:start + m] = (centers[j] + stds[j] * z).astype(np.float32)
-        start += m
     if shuffle:
-        perm = g.permutation(n)
-        X = X[perm]
-        truth = truth[perm]
+        truth = truth[g.permutation(n)]
+    # one draw for all points, in their final order: X = centre + std * z
+    X = g.standard_normal(size=(n, d), dtype=np.float32)
+    X *= stds.astype(np.float32)[truth][:, None]
+    X += centers.astype(np.float32)[truth]
     return np.ascontiguousarray(X), truth, centers
 
 
