@@ -125,10 +125,13 @@ AssignPlan plan_assign(const km_precision& p, int64_t n, int d, int k) {
   a.alpha_f = alpha < 0.0 ? 0.0f : (float)std::min(alpha, 1e30);
   a.oma = 1.0f - a.alpha_f;
   if (a.route == Route::Mfma) a.alpha_used = (double)a.alpha_f;
-  if (a.route == Route::Direct64Exact || a.route == Route::Direct64All)
+  if (a.route == Route::Direct64Exact || a.route == Route::Direct64All) {
     a.nwg = (int)((n + kDirectPointsPerWg - 1) / kDirectPointsPerWg);
-  else
-    a.nwg = (int)((n + mfma_points_per_wg(p.low, a.DP) - 1) / mfma_points_per_wg(p.low, a.DP));
+    a.nwg_pair = a.nwg;
+  } else {
+    a.nwg = (int)((n + pipe_points_per_wg(p.low, a.DP) - 1) / pipe_points_per_wg(p.low, a.DP));
+    a.nwg_pair = (int)((n + mfma_points_per_wg(p.low, a.DP) - 1) / mfma_points_per_wg(p.low, a.DP));
+  }
   return a;
 }
 
@@ -371,8 +374,8 @@ void plan_pass(Plan& pl, const AssignPlan& a) {
   pl.add<char>((size_t)a.k_pad * a.DP * 4);
   pl.add<float>(a.k_pad);
   pl.add<float>(a.k_pad);
-  pl.add<double>(a.nwg);
-  pl.add<unsigned long long>(a.nwg);
+  pl.add<double>(std::max(a.nwg, a.nwg_pair));
+  pl.add<unsigned long long>(std::max(a.nwg, a.nwg_pair));
   pl.add<int>(1);
   pl.add<KResult>(1);
 }
@@ -382,8 +385,8 @@ PassBufs carve_pass(Arena& ar, const AssignPlan& a) {
   b.Cq = ar.take<char>((size_t)a.k_pad * a.DP * 4);
   b.cinit = ar.take<float>(a.k_pad);
   b.ca = ar.take<float>(a.k_pad);
-  b.sse_part = ar.take<double>(a.nwg);
-  b.corr_part = ar.take<unsigned long long>(a.nwg);
+  b.sse_part = ar.take<double>(std::max(a.nwg, a.nwg_pair));
+  b.corr_part = ar.take<unsigned long long>(std::max(a.nwg, a.nwg_pair));
   b.status = ar.take<int>(1);
   b.result = ar.take<KResult>(1);
   return b;
@@ -429,7 +432,8 @@ static hipError_t enqueue_pass(km_context_impl* ctx, const AssignPlan& a, const 
   ap.k = k;
   ap.k_pad = a.k_pad;
   ap.oma = a.oma;
-  hipError_t e = run_assign(ctx, a, mode, {ap}, {a.nwg}, st);
+  const int nwg = mode == 0 ? a.nwg : a.nwg_pair;
+  hipError_t e = run_assign(ctx, a, mode, {ap}, {nwg}, st);
   if (e != hipSuccess) return e;
   ReduceProb rp{};
   rp.sse_part = b.sse_part;
@@ -438,7 +442,7 @@ static hipError_t enqueue_pass(km_context_impl* ctx, const AssignPlan& a, const 
   rp.sse_out = sse_slot;
   rp.result = b.result;
   rp.pairs = n * (long long)k;
-  rp.nparts = a.nwg;
+  rp.nparts = nwg;
   return run_reduce(ctx, {rp}, st);
 }
 

@@ -129,9 +129,9 @@ k_prep_centroids(const PrepProb* __restrict__ probs, const int32_t* __restrict__
 // MODE 0: argmin + refinement + partials.  MODE 1: write every pair's value
 // and flag (materialised distances for reports and tests).
 // ---------------------------------------------------------------------------
-template <class L, int DP, int NB>
+template <class L, int DP, int NB, int WAVES = 4>
 struct AssignCfg {
-  static constexpr int kWaves = 4;
+  static constexpr int kWaves = WAVES;
   static constexpr int kPts = kWaves * NB * 32;           // points per workgroup
   static constexpr int kLd = DP + (L::KS == 2 ? 4 : 8);   // LDS row stride (elements)
   static constexpr int kCt = 64;                          // centres per LDS tile
@@ -139,7 +139,7 @@ struct AssignCfg {
   static constexpr int kBytes = 2 * kCt * kLd * (int)sizeof(typename L::S);
   // 16-byte chunks of one centre tile in global memory
   static constexpr int kChunks = kCt * DP * (int)sizeof(typename L::S) / 16;
-  static constexpr int kChunksPerThread = (kChunks + 255) / 256;
+  static constexpr int kChunksPerThread = (kChunks + kWaves * 64 - 1) / (kWaves * 64);
   static constexpr int kElemsPerChunk = 16 / (int)sizeof(typename L::S);
 };
 
@@ -511,9 +511,10 @@ k_assign_mfma(const AssignProb* __restrict__ probs, const int32_t* __restrict__ 
 // lives in LDS and is written only when the lane's best value improves.
 // ---------------------------------------------------------------------------
 template <class L, int DP, int NB, bool FALLBACK>
-__global__ void __launch_bounds__(256, 2)
+__global__ void __launch_bounds__(kPipeThreads, 1)
 k_assign_pipe(const AssignProb* __restrict__ probs, const int32_t* __restrict__ wg_start, int nprob) {
-  using Cfg = AssignCfg<L, DP, NB>;
+  using Cfg = AssignCfg<L, DP, NB, kPipeWaves>;
+  constexpr int NT = kPipeThreads;
   using S = typename L::S;
   constexpr int LD = Cfg::kLd;
   constexpr int CT = Cfg::kCt;
@@ -522,8 +523,8 @@ k_assign_pipe(const AssignProb* __restrict__ probs, const int32_t* __restrict__ 
   __shared__ __attribute__((aligned(16))) unsigned char smem[Cfg::kBytes];
   __shared__ float s_cinit[2][CT];
   __shared__ float s_ca[3][CT];
-  __shared__ f32x4 s_sv[4][NB][4][64];  // saved best block: [wave][cb][r/4][lane]
-  __shared__ int s_q[FALLBACK ? kQueue * 256 : 1];
+  __shared__ f32x4 s_sv[kPipeWaves][NB][4][64];  // saved best block: [wave][cb][r/4][lane]
+  __shared__ int s_q[FALLBACK ? kQueue * NT : 1];
   __shared__ double s_sse[Cfg::kWaves];
   __shared__ unsigned long long s_corr[Cfg::kWaves];
 
@@ -605,7 +606,7 @@ k_assign_pipe(const AssignProb* __restrict__ probs, const int32_t* __restrict__ 
   auto flush_queue = [&]() {
     if constexpr (FALLBACK) {
       for (int q = 0; q < qn; ++q) {
-        const int e = s_q[q * 256 + tid];
+        const int e = s_q[q * NT + tid];
         const int j = e & 0xffffff;
         const int cbq = e >> 24;
         const int pl = pw + cbq * 32 + (lane & 31);
@@ -636,7 +637,7 @@ k_assign_pipe(const AssignProb* __restrict__ probs, const int32_t* __restrict__ 
     const int nchunk = rows * DP / Cfg::kElemsPerChunk;
 #pragma unroll
     for (int u = 0; u < Cfg::kChunksPerThread; ++u) {
-      const int c = tid + u * 256;
+      const int c = tid + u * NT;
       if (c < nchunk) stage[u] = g[c];
     }
     if (tid < rows) {
@@ -651,7 +652,7 @@ k_assign_pipe(const AssignProb* __restrict__ probs, const int32_t* __restrict__ 
     S* dst = sc0 + (t & 1) * CT * LD;
 #pragma unroll
     for (int u = 0; u < Cfg::kChunksPerThread; ++u) {
-      const int c = tid + u * 256;
+      const int c = tid + u * NT;
       if (c < nchunk) {
         const int row = c / CPR, col = (c % CPR) * Cfg::kElemsPerChunk;
         *reinterpret_cast<f32x4*>(dst + row * LD + col) = stage[u];
@@ -663,24 +664,37 @@ k_assign_pipe(const AssignProb* __restrict__ probs, const int32_t* __restrict__ 
     }
   };
 
-  // MFMAs of one 32-centre block: acc = -nc/2 + x~^T c~
-  auto issue = [&](f32x16 (&acc)[NB], int t, int bk) {
-    const S* arow = sc0 + (t & 1) * CT * LD + (bk * 32 + (lane & 31)) * LD + (lane >> 5) * L::KV;
-    typename L::frag af[Cfg::kSteps];
+  // A fragments of one 32-centre block (8 consecutive K values per lane and
+  // K step) from the LDS tile
+  typename L::frag af[Cfg::kSteps];
+  auto afrag_ptr = [&](int t, int bk) {
+    return sc0 + (t & 1) * CT * LD + (bk * 32 + (lane & 31)) * LD + (lane >> 5) * L::KV;
+  };
+  auto load_af = [&](int t, int bk) {
+    const S* arow = afrag_ptr(t, bk);
 #pragma unroll
     for (int s = 0; s < Cfg::kSteps; ++s) {
       if constexpr (L::KV == 1) af[s] = arow[s * L::KS];
       else af[s] = *reinterpret_cast<const typename L::frag*>(arow + s * L::KS);
     }
+  };
+  // MFMAs of one 32-centre block: acc = -nc/2 + x~^T c~, from the fragments
+  // in af; when `pre` is set, each K step's fragment register is refilled
+  // with the next block's (tn, bkn) fragment right after its last use
+  auto issue = [&](f32x16 (&acc)[NB], int t, int bk, bool pre, int tn, int bkn) {
     f32x16 ci;
 #pragma unroll
     for (int r = 0; r < 16; ++r) ci[r] = s_cinit[t & 1][bk * 32 + acc_row(r, lane)];
+    const S* nrow = afrag_ptr(tn, bkn);
 #pragma unroll
-    for (int cb = 0; cb < NB; ++cb) acc[cb] = L::mfma(af[0], bfr[cb][0], ci);
+    for (int s = 0; s < Cfg::kSteps; ++s) {
 #pragma unroll
-    for (int s = 1; s < Cfg::kSteps; ++s)
-#pragma unroll
-      for (int cb = 0; cb < NB; ++cb) acc[cb] = L::mfma(af[s], bfr[cb][s], acc[cb]);
+      for (int cb = 0; cb < NB; ++cb) acc[cb] = L::mfma(af[s], bfr[cb][s], s == 0 ? ci : acc[cb]);
+      if (pre) {
+        if constexpr (L::KV == 1) af[s] = nrow[s * L::KS];
+        else af[s] = *reinterpret_cast<const typename L::frag*>(nrow + s * L::KS);
+      }
+    }
   };
   // epilogue part 1 (overlaps the next block's MFMAs): block maxima of the
   // test quantity W + ca and of W
@@ -719,7 +733,7 @@ k_assign_pipe(const AssignProb* __restrict__ probs, const int32_t* __restrict__ 
             const int j = jb + acc_row(r, lane);
             if (j >= P.k) continue;
             if (qn < kQueue) {
-              s_q[qn * 256 + tid] = j | (cb << 24);
+              s_q[qn * NT + tid] = j | (cb << 24);
               qn += 1;
             } else {  // queue full (dense flags): correct this pair now
               const float df = (float)sqdist64_call(P.X + (p0 + pl) * d, P.C + (int64_t)j * d, d);
@@ -760,9 +774,10 @@ k_assign_pipe(const AssignProb* __restrict__ probs, const int32_t* __restrict__ 
   // tile 0
   const int nbk0 = (kpad < CT ? kpad : CT) / 32;
   if (1 < ntile) load_tile(1);
-  issue(accA, 0, 0);
+  load_af(0, 0);
+  issue(accA, 0, 0, nbk0 == 2, 0, 1);
   if (nbk0 == 2) {
-    issue(accB, 0, 1);
+    issue(accB, 0, 1, false, 0, 0);
     epi1(accA, 0, 0, tm, wm);
     KM_INTERLEAVE();
     epi2(accA, 0, 0, tm, wm);
@@ -772,13 +787,14 @@ k_assign_pipe(const AssignProb* __restrict__ probs, const int32_t* __restrict__ 
   // tiles 1..: every tile before the last holds two blocks
   for (int t = 1; t < ntile; ++t) {
     if (t + 1 < ntile) load_tile(t + 1);
-    issue(accA, t, 0);
+    const int nbk = ((kpad - t * CT) < CT ? (kpad - t * CT) : CT) / 32;
+    load_af(t, 0);
+    issue(accA, t, 0, nbk == 2, t, 1);
     epi1(accB, t - 1, 1, tm, wm);
     KM_INTERLEAVE();
     epi2(accB, t - 1, 1, tm, wm);
-    const int nbk = ((kpad - t * CT) < CT ? (kpad - t * CT) : CT) / 32;
     if (nbk == 2) {
-      issue(accB, t, 1);
+      issue(accB, t, 1, false, t, 0);
       epi1(accA, t, 0, tm, wm);
       KM_INTERLEAVE();
       epi2(accA, t, 0, tm, wm);
@@ -1073,9 +1089,9 @@ static hipError_t launch_mfma_t(int mode, bool fallback, const AssignProb* dprob
                                 int nprob, int nwg, hipStream_t st) {
   if (mode == 0) {
     if (fallback)
-      hipLaunchKernelGGL((k_assign_pipe<L, DP, NB, true>), dim3(nwg), dim3(256), 0, st, dprobs, dstart, nprob);
+      hipLaunchKernelGGL((k_assign_pipe<L, DP, NB, true>), dim3(nwg), dim3(kPipeThreads), 0, st, dprobs, dstart, nprob);
     else
-      hipLaunchKernelGGL((k_assign_pipe<L, DP, NB, false>), dim3(nwg), dim3(256), 0, st, dprobs, dstart, nprob);
+      hipLaunchKernelGGL((k_assign_pipe<L, DP, NB, false>), dim3(nwg), dim3(kPipeThreads), 0, st, dprobs, dstart, nprob);
   } else {
     if (fallback)
       hipLaunchKernelGGL((k_assign_mfma<L, DP, NB, 1, true>), dim3(nwg), dim3(256), 0, st, dprobs, dstart, nprob);

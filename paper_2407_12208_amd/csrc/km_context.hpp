@@ -98,6 +98,7 @@ struct AssignPlan {
   int DP;
   int k_pad;
   int nwg;          // workgroups of the assignment kernel
+  int nwg_pair;     // workgroups of the materialising kernel
   float alpha_f;    // alpha as applied (FP32)
   float oma;        // 1 - alpha (FP32)
   double alpha_used;

@@ -30,6 +30,10 @@ constexpr int mfma_nb(int low, int DP) {
   return low == kLowFP32 ? (DP <= 32 ? 2 : 1) : (DP <= 128 ? 2 : 1);
 }
 constexpr int mfma_points_per_wg(int low, int DP) { return 4 * 32 * mfma_nb(low, DP); }
+// workgroup of the pipelined assignment kernel
+constexpr int kPipeWaves = 8;
+constexpr int kPipeThreads = 64 * kPipeWaves;
+constexpr int pipe_points_per_wg(int low, int DP) { return kPipeWaves * 32 * mfma_nb(low, DP); }
 constexpr int kDirectPointsPerWg = 64;
 
 // Accumulated per-problem results on the device.
