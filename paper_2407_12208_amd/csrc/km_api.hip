@@ -129,7 +129,7 @@ AssignPlan plan_assign(const km_precision& p, int64_t n, int d, int k) {
     a.nwg = (int)((n + kDirectPointsPerWg - 1) / kDirectPointsPerWg);
     a.nwg_pair = a.nwg;
   } else {
-    a.nwg = (int)((n + pipe_points_per_wg(p.low, a.DP) - 1) / pipe_points_per_wg(p.low, a.DP));
+    a.nwg = (int)((n + assign_points_per_wg(p.low, a.DP) - 1) / assign_points_per_wg(p.low, a.DP));
     a.nwg_pair = (int)((n + mfma_points_per_wg(p.low, a.DP) - 1) / mfma_points_per_wg(p.low, a.DP));
   }
   return a;

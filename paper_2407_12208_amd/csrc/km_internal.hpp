@@ -34,6 +34,14 @@ constexpr int mfma_points_per_wg(int low, int DP) { return 4 * 32 * mfma_nb(low,
 constexpr int kPipeWaves = 8;
 constexpr int kPipeThreads = 64 * kPipeWaves;
 constexpr int pipe_points_per_wg(int low, int DP) { return kPipeWaves * 32 * mfma_nb(low, DP); }
+// one-wave-per-SIMD assignment kernel (16-bit formats, DP <= 128): 4 waves of
+// ring_nb(DP) 32-point column blocks
+constexpr bool uses_ring(int low, int DP) { return low != kLowFP32 && DP <= 128; }
+constexpr int ring_nb(int DP) { return DP <= 128 ? 4 : 2; }
+// points per workgroup of the assignment-mode kernel
+constexpr int assign_points_per_wg(int low, int DP) {
+  return uses_ring(low, DP) ? 4 * 32 * ring_nb(DP) : pipe_points_per_wg(low, DP);
+}
 constexpr int kDirectPointsPerWg = 64;
 
 // Accumulated per-problem results on the device.
@@ -117,7 +125,7 @@ hipError_t launch_quantize(int low, const float* in, int64_t count, uint16_t* ou
 
 // centre update (km_update.hip)
 constexpr int kUpdTile = 1024;   // points per histogram / scatter tile
-constexpr int kUpdChunk = 256;   // members per partial sum
+constexpr int kUpdChunk = 64;    // members per partial sum
 hipError_t launch_update(const UpdateProb* dprobs, const UpdateProb* hprobs, int nprob,
                          const int32_t* dscratch_i32, hipStream_t st);
 

@@ -12,7 +12,7 @@
 //   3. scan_cl   per problem, cluster starts and chunk starts;
 //   4. scatter   stable counting sort of point indices by label: members of
 //                a cluster appear in ascending point order;
-//   5. chunksum  one wave per chunk of <= 256 consecutive members of one
+//   5. chunksum  one wave per chunk of <= 64 consecutive members of one
 //                cluster: FP64 sums over fixed member groups, combined by a
 //                fixed butterfly;
 //   6. finalize  per cluster, sum of its chunk partials in order, division,
@@ -140,11 +140,13 @@ k_upd_scan_cl(const UpdateProb* __restrict__ probs) {
 }
 
 // 4. stable scatter of point indices into cluster order.  One wave per
-// 1024-point tile walks the tile in 16 rounds of 64 points; inside a round
-// the lanes holding one label are found with a ballot loop (one iteration per
-// distinct label), ranked by lane order, and placed after the earlier rounds'
-// points of that label (per-wave counters in LDS).  Members of a cluster thus
-// appear in ascending point order.  k > kScatterLds uses the brute-force rank.
+// 1024-point tile walks the tile in 16 rounds of 64 points.  In a round each
+// lane finds the lanes holding its label from one ballot per label bit (the
+// lanes that agree with it on every bit), ranks itself among them by lane
+// order and is placed after the earlier rounds' points of that label
+// (per-wave counters in LDS, advanced by the group's lowest lane).  Members
+// of a cluster thus appear in ascending point order.  k > kScatterLds uses
+// the brute-force rank.
 constexpr int kScatterLds = 4096;
 
 __global__ void __launch_bounds__(256)
@@ -161,25 +163,28 @@ k_upd_scatter(const UpdateProb* __restrict__ probs, const int32_t* __restrict__ 
     int* c = cnt[wave];
     // running output position of each cluster for this tile
     for (int j = lane; j < P.k; j += 64) c[j] = P.cstart[j] + P.offs[(int64_t)j * P.ntiles + tile];
+    int nbits = 0;
+    while ((1 << nbits) < P.k) ++nbits;
     const unsigned long long below = (1ull << lane) - 1;
     for (int r0 = 0; r0 < m; r0 += 64) {
       const int i = r0 + lane;
       const int lab = i < m ? P.labels[p0 + i] : -1;
       const bool ok = lab >= 0 && lab < P.k;
-      unsigned long long todo = __ballot(ok);
-      while (todo) {
-        const int leader = __ffsll((long long)todo) - 1;
-        const int L = __shfl(lab, leader, kWave);
-        const unsigned long long grp = __ballot(ok && lab == L);
-        if (ok && lab == L) {
-          const int rank = __popcll(grp & below);
-          P.perm[c[L] + rank] = (int32_t)(p0 + i);
-        }
-        // every lane of the group has read c[L] above before the leader
-        // writes it (the wave executes the read before the write)
-        if (lane == leader) c[L] += __popcll(grp);
-        todo &= ~grp;
+      unsigned long long grp = __ballot(ok);
+      for (int b = 0; b < nbits; ++b) {
+        const bool bit = (lab >> b) & 1;
+        const unsigned long long mb = __ballot(ok && bit);
+        grp &= bit ? mb : ~mb;
       }
+      // grp: the valid lanes whose label equals this lane's (this lane
+      // included when ok)
+      if (ok) {
+        const int base = c[lab];
+        P.perm[base + __popcll(grp & below)] = (int32_t)(p0 + i);
+      }
+      // every lane of the round has read its counter above before any
+      // group leader writes it (the wave executes the reads first)
+      if (ok && (grp & below) == 0) c[lab] += __popcll(grp);
     }
   } else {
     for (int i = lane; i < m; i += 64) {
@@ -193,11 +198,96 @@ k_upd_scatter(const UpdateProb* __restrict__ probs, const int32_t* __restrict__ 
   }
 }
 
-// 5. one wave per chunk of <= 256 members of one cluster.  Lanes are split
-// into G member groups x DPW coordinate slots (DPW = next power of two >= d
-// when d <= 64, else 64 with several coordinates per lane); each lane sums its
-// group's members (every G-th member, ascending) in FP64, then the groups are
-// combined by a fixed butterfly.  The order depends only on the chunk.
+// 5. one wave per chunk of <= 64 members of one cluster.  Lanes are split
+// into G member groups x L lanes per member row; each lane sums its group's
+// members (every G-th member, ascending) in FP64 over its coordinates, then
+// the groups are combined by a fixed butterfly.  The order depends only on
+// the chunk.  Rows of 16-byte aligned data with d % 4 == 0 are read as float4
+// (L = lanes for d/4 vectors, rounded up to a power of two), other rows one
+// coordinate per lane (L = lanes for d, up to 64, several coordinates per
+// lane beyond 64).
+template <bool VEC>
+__device__ inline void chunk_rows(const UpdateProb& P, int c, int m0, int m1, int lane) {
+  const int d = P.d;
+  const int per = VEC ? 4 : 1;              // coordinates per load
+  const int nv = (d + per - 1) / per;       // loads per row
+  int L = 1;
+  while (L < nv && L < 64) L <<= 1;
+  const int G = 64 / L;                     // member groups
+  const int g = lane / L, cl = lane % L;
+  constexpr int kMaxSlots = VEC ? 1 : 4;    // VEC: d <= 256 -> <= 64 vectors
+  const int nslot = (nv + 63) / 64;
+  double s[kMaxSlots][4];
+#pragma unroll
+  for (int q = 0; q < kMaxSlots; ++q)
+#pragma unroll
+    for (int e = 0; e < 4; ++e) s[q][e] = 0.0;
+  const float* __restrict__ X = P.X;
+  auto add_row = [&](int id) {
+#pragma unroll
+    for (int q = 0; q < kMaxSlots; ++q) {
+      if (q >= nslot) break;
+      const int v = cl + 64 * q;
+      if (v >= nv) continue;
+      if constexpr (VEC) {
+        const float4 x = *reinterpret_cast<const float4*>(X + (int64_t)id * d + 4 * v);
+        s[q][0] += (double)x.x;
+        s[q][1] += (double)x.y;
+        s[q][2] += (double)x.z;
+        s[q][3] += (double)x.w;
+      } else {
+        s[q][0] += (double)X[(int64_t)id * d + v];
+      }
+    }
+  };
+  int mm = m0 + g;
+  // 8 members per group and batch: all their loads are independent
+  for (; mm + 7 * G < m1; mm += 8 * G) {
+    int idx[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) idx[u] = P.perm[mm + u * G];
+    if constexpr (VEC) {
+      float4 xv[8];
+      const int v = cl;
+      const bool on = v < nv;
+#pragma unroll
+      for (int u = 0; u < 8; ++u)
+        xv[u] = on ? *reinterpret_cast<const float4*>(X + (int64_t)idx[u] * d + 4 * v) : make_float4(0.f, 0.f, 0.f, 0.f);
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        s[0][0] += (double)xv[u].x;
+        s[0][1] += (double)xv[u].y;
+        s[0][2] += (double)xv[u].z;
+        s[0][3] += (double)xv[u].w;
+      }
+    } else {
+#pragma unroll
+      for (int u = 0; u < 8; ++u) add_row(idx[u]);
+    }
+  }
+  for (; mm < m1; mm += G) add_row(P.perm[mm]);
+  // combine the G groups (fixed butterfly over the group bits)
+  for (int o = L; o < 64; o <<= 1) {
+#pragma unroll
+    for (int q = 0; q < kMaxSlots; ++q)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) s[q][e] += __shfl_xor(s[q][e], o, kWave);
+  }
+  if (g == 0) {
+#pragma unroll
+    for (int q = 0; q < kMaxSlots; ++q) {
+      if (q >= nslot) break;
+      const int v = cl + 64 * q;
+      if (v >= nv) continue;
+#pragma unroll
+      for (int e = 0; e < per; ++e) {
+        const int l = per * v + e;
+        if (l < d) P.chunk_sum[(int64_t)c * d + l] = s[q][e];
+      }
+    }
+  }
+}
+
 __global__ void __launch_bounds__(256)
 k_upd_chunksum(const UpdateProb* __restrict__ probs, const int32_t* __restrict__ wg_start, int nprob) {
   const int pi = find_prob(wg_start, nprob, blockIdx.x);
@@ -214,54 +304,10 @@ k_upd_chunksum(const UpdateProb* __restrict__ probs, const int32_t* __restrict__
   const int j = lo;
   const int m0 = P.cstart[j] + (c - P.chunk_start[j]) * kUpdChunk;
   const int m1 = (m0 + kUpdChunk) < P.cstart[j + 1] ? (m0 + kUpdChunk) : P.cstart[j + 1];
-  const int d = P.d;
-  int dpw = 1;
-  while (dpw < d && dpw < 64) dpw <<= 1;
-  const int G = 64 / dpw;            // member groups
-  const int g = lane / dpw, cl = lane % dpw;
-  constexpr int kMaxSlots = 4;       // d <= 256
-  const int nslot = (d + 63) / 64;   // coordinates per lane when d > 64
-  double s[kMaxSlots] = {0.0, 0.0, 0.0, 0.0};
-  const float* __restrict__ X = P.X;
-  int mm = m0 + g;
-  // 8 members per batch of independent loads
-  for (; mm + 7 * G < m1; mm += 8 * G) {
-    int idx[8];
-#pragma unroll
-    for (int u = 0; u < 8; ++u) idx[u] = P.perm[mm + u * G];
-#pragma unroll
-    for (int q = 0; q < kMaxSlots; ++q) {
-      if (q >= nslot) break;
-      const int l = cl + 64 * q;
-      float v[8];
-#pragma unroll
-      for (int u = 0; u < 8; ++u) v[u] = (l < d) ? X[(int64_t)idx[u] * d + l] : 0.0f;
-#pragma unroll
-      for (int u = 0; u < 8; ++u) s[q] += (double)v[u];
-    }
-  }
-  for (; mm < m1; mm += G) {
-    const int id = P.perm[mm];
-#pragma unroll
-    for (int q = 0; q < kMaxSlots; ++q) {
-      if (q >= nslot) break;
-      const int l = cl + 64 * q;
-      if (l < d) s[q] += (double)X[(int64_t)id * d + l];
-    }
-  }
-  // combine the G groups (fixed butterfly over the group bits)
-  for (int o = dpw; o < 64; o <<= 1) {
-#pragma unroll
-    for (int q = 0; q < kMaxSlots; ++q) s[q] += __shfl_xor(s[q], o, kWave);
-  }
-  if (g == 0) {
-#pragma unroll
-    for (int q = 0; q < kMaxSlots; ++q) {
-      if (q >= nslot) break;
-      const int l = cl + 64 * q;
-      if (l < d) P.chunk_sum[(int64_t)c * d + l] = s[q];
-    }
-  }
+  if ((P.d & 3) == 0 && (((uintptr_t)P.X) & 15) == 0)
+    chunk_rows<true>(P, c, m0, m1, lane);
+  else
+    chunk_rows<false>(P, c, m0, m1, lane);
 }
 
 // 6. per cluster: ordered sum of chunk partials, divide, round, keep empty
