@@ -93,6 +93,43 @@ def serve_bench(km, ctx, count, seed):
     return out
 
 
+KERNEL_SOURCES = ("paper_2407_12208_amd/csrc/km_assign.hip",
+                  "paper_2407_12208_amd/csrc/km_device.hpp",
+                  "paper_2407_12208_amd/csrc/km_internal.hpp")
+TRAFFIC_RECORD = "profiles/k_assign_pipe_fp16_n1e6_d128_k4096_hbm_traffic.md"
+
+
+def kernel_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for rel in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def measured_traffic():
+    """HBM bytes per assignment launch from the committed counter record
+    (FETCH_SIZE + WRITE_SIZE, each scaled by the same counter's reading for a
+    plain copy of known size), or None when the record is missing or was
+    taken on different kernel sources."""
+    path = os.path.join(ROOT, TRAFFIC_RECORD)
+    if not os.path.exists(path):
+        return None
+    rec = {}
+    with open(path) as f:
+        for line in f:
+            if ":" in line and line.startswith("- "):
+                key, val = line[2:].split(":", 1)
+                rec[key.strip()] = val.strip().strip("`")
+    try:
+        if rec.get("kernel_source_sha256") != kernel_source_hash():
+            return None
+        return float(rec["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -177,7 +214,7 @@ def main():
                    "alpha_form": "equation (2 rho gamma)", "rho": 5.0},
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": MFMA_FP16_PEAK_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / MFMA_FP16_PEAK_TFLOPS,
-                     "traffic": None,
+                     "traffic": measured_traffic(),
                      "kernel": "k_assign_pipe<LowF16,128,2,true>",
                      "kernel_avg_ms": kern_avg_ms,
                      "algorithmic_flops_per_launch": flops},
@@ -228,11 +265,13 @@ def main():
         log("extra: %s" % json.dumps(extra))
 
     if args.calib_copy_mib > 0:
+        # one elementwise kernel that reads and writes `nbytes` each: the
+        # reference for the HBM byte counters
         nbytes = args.calib_copy_mib << 20
         a = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda").fill_(1.0)
         b = torch.empty_like(a)
         torch.cuda.synchronize()
-        b.copy_(a)
+        torch.mul(a, 1.0, out=b)
         torch.cuda.synchronize()
         out["calib_copy_bytes"] = nbytes
 

@@ -23,9 +23,6 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-    # MFMA results and accumulator inputs in architectural VGPRs (the fused
-    # epilogues read every accumulator with vector ALU instructions)
-    "-mllvm", "--amdgpu-mfma-vgpr-form",
     "-I" + os.path.join(ROOT, "include"), "-I" + CSRC,
     "-Wall", "-Wno-unused-function", "-Wno-unused-variable",
 ]

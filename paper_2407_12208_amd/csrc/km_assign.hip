@@ -81,16 +81,16 @@ __device__ inline double refine_wave(const AssignProb& P, int64_t pbase, int nlo
     const int q = q0 + (lane >> 4);
     const bool on = q < nloc;
     const int lab = on ? labs[q] : 0;
-    const float* xr = P.X + (pbase + (on ? q : 0)) * d;
-    const float* cr = P.C + (int64_t)lab * d;
+    const KM_GLOBAL float* xr = as_global(P.X) + (pbase + (on ? q : 0)) * d;
+    const KM_GLOBAL float* cr = as_global(P.C) + (int64_t)lab * d;
     double part = 0.0;
     for (int l0 = 8 * sub; l0 < d; l0 += 128) {
       if (vec) {
 #pragma unroll
         for (int h = 0; h < 8; h += 4) {
           if (l0 + h < d) {
-            const float4 a = *reinterpret_cast<const float4*>(xr + l0 + h);
-            const float4 b = *reinterpret_cast<const float4*>(cr + l0 + h);
+            const f32x4 a = *reinterpret_cast<const KM_GLOBAL f32x4*>(xr + l0 + h);
+            const f32x4 b = *reinterpret_cast<const KM_GLOBAL f32x4*>(cr + l0 + h);
             const double e0 = (double)a.x - (double)b.x, e1 = (double)a.y - (double)b.y;
             const double e2 = (double)a.z - (double)b.z, e3 = (double)a.w - (double)b.w;
             part = __builtin_fma(e0, e0, part);
@@ -109,7 +109,7 @@ __device__ inline double refine_wave(const AssignProb& P, int64_t pbase, int nlo
 #pragma unroll
     for (int o = 8; o >= 1; o >>= 1) part += __shfl_xor(part, o, kWave);
     if (on && sub == 0) {
-      if (P.mindist) P.mindist[pbase + q] = (float)part;
+      if (P.mindist) as_global(P.mindist)[pbase + q] = (float)part;
       sse += part;
     }
   }
@@ -137,14 +137,14 @@ k_prep_centroids(const PrepProb* __restrict__ probs, const int32_t* __restrict__
   const int lane = threadIdx.x & 63;
   const int j = (blockIdx.x - wg_start[pi]) * 4 + (threadIdx.x >> 6);
   if (j >= P.k_pad) return;
-  typename L::S* out = reinterpret_cast<typename L::S*>(P.Cq) + (int64_t)j * P.DP;
+  KM_GLOBAL typename L::S* out = reinterpret_cast<KM_GLOBAL typename L::S*>(as_global(P.Cq)) + (int64_t)j * P.DP;
   int bad = 0;
   float s = 0.0f;
   const bool valid = j < P.k;
   for (int l = lane; l < P.DP; l += 64) {
     float v = 0.0f;
     if (valid && l < P.d) {
-      v = P.C[(int64_t)j * P.d + l];
+      v = as_global(P.C)[(int64_t)j * P.d + l];
       if (!__builtin_isfinite(v)) bad |= kStatusNonFinite;
       if (L::kHasRange && __builtin_fabsf(v) >= L::kOverflow) bad |= kStatusRange;
     }
@@ -158,11 +158,11 @@ k_prep_centroids(const PrepProb* __restrict__ probs, const int32_t* __restrict__
   if (lane == 0) {
     if (valid) {
       const float hc = 0.5f * s;
-      P.cinit[j] = -hc;
-      P.ca[j] = P.alpha * hc;
+      as_global(P.cinit)[j] = -hc;
+      as_global(P.ca)[j] = P.alpha * hc;
     } else {
-      P.cinit[j] = -__builtin_inff();
-      P.ca[j] = 0.0f;
+      as_global(P.cinit)[j] = -__builtin_inff();
+      as_global(P.ca)[j] = 0.0f;
     }
   }
   raise_status(P.status, bad);
@@ -237,7 +237,7 @@ k_assign_mfma(const AssignProb* __restrict__ probs, const int32_t* __restrict__ 
   for (int cb = 0; cb < NB; ++cb) {
     const int pl = pw + cb * 32 + (lane & 31);
     const bool pv = pl < nvalid;
-    const float* xr = P.X + (p0 + (pv ? pl : 0)) * d;
+    const KM_GLOBAL float* xr = as_global(P.X) + (p0 + (pv ? pl : 0)) * d;
     float part = 0.0f;
 #pragma unroll
     for (int s = 0; s < Cfg::kSteps; ++s) {
@@ -247,15 +247,15 @@ k_assign_mfma(const AssignProb* __restrict__ probs, const int32_t* __restrict__ 
         if (fast) {
 #pragma unroll
           for (int u = 0; u < L::KV; u += 4) {
-            const f32x4 q = *reinterpret_cast<const f32x4*>(xr + o + u);
+            const f32x4 q = *reinterpret_cast<const KM_GLOBAL f32x4*>(xr + o + u);
             v[u] = q[0]; v[u + 1] = q[1]; v[u + 2] = q[2]; v[u + 3] = q[3];
           }
         } else if (vec4) {
 #pragma unroll
           for (int u = 0; u < L::KV; u += 4) {
-            float4 q = make_float4(0.f, 0.f, 0.f, 0.f);
-            if (pv && o + u < d) q = *reinterpret_cast<const float4*>(xr + o + u);
-            v[u] = q.x; v[u + 1] = q.y; v[u + 2] = q.z; v[u + 3] = q.w;
+            f32x4 q = {0.f, 0.f, 0.f, 0.f};
+            if (pv && o + u < d) q = *reinterpret_cast<const KM_GLOBAL f32x4*>(xr + o + u);
+            v[u] = q[0]; v[u + 1] = q[1]; v[u + 2] = q[2]; v[u + 3] = q[3];
           }
         } else {
 #pragma unroll
@@ -330,8 +330,8 @@ k_assign_mfma(const AssignProb* __restrict__ probs, const int32_t* __restrict__ 
             }
           } else {
             const int64_t o = (p0 + pl) * (int64_t)P.k + j;
-            P.D[o] = df;
-            if (P.flagged) P.flagged[o] = 1;
+            as_global(P.D)[o] = df;
+            if (P.flagged) as_global(P.flagged)[o] = 1;
           }
         }
       }
@@ -341,14 +341,14 @@ k_assign_mfma(const AssignProb* __restrict__ probs, const int32_t* __restrict__ 
 
   const int kpad = P.k_pad;
   const int ntile = (kpad + CT - 1) / CT;
-  const S* Cq = reinterpret_cast<const S*>(P.Cq);
+  const KM_GLOBAL S* Cq = reinterpret_cast<const KM_GLOBAL S*>(as_global(P.Cq));
 
   // global -> register staging of one centre tile (16-byte chunks)
   f32x4 stage[Cfg::kChunksPerThread];
   float st_ci = 0.f, st_ca = 0.f;
   auto load_tile = [&](int t) {
     const int rows = (kpad - t * CT) < CT ? (kpad - t * CT) : CT;
-    const f32x4* g = reinterpret_cast<const f32x4*>(Cq + (int64_t)t * CT * DP);
+    const KM_GLOBAL f32x4* g = reinterpret_cast<const KM_GLOBAL f32x4*>(Cq + (int64_t)t * CT * DP);
     const int nchunk = rows * DP / Cfg::kElemsPerChunk;
 #pragma unroll
     for (int u = 0; u < Cfg::kChunksPerThread; ++u) {
@@ -356,8 +356,8 @@ k_assign_mfma(const AssignProb* __restrict__ probs, const int32_t* __restrict__ 
       if (c < nchunk) stage[u] = g[c];
     }
     if (tid < rows) {
-      st_ci = P.cinit[t * CT + tid];
-      st_ca = P.ca[t * CT + tid];
+      st_ci = as_global(P.cinit)[t * CT + tid];
+      st_ca = as_global(P.ca)[t * CT + tid];
     }
   };
   auto store_tile = [&](int t, int buf) {
@@ -454,8 +454,8 @@ k_assign_mfma(const AssignProb* __restrict__ probs, const int32_t* __restrict__ 
             if (flag) fmask[bk][cb] |= 1u << r;
             if (!flag && pl < nvalid && j < P.k) {
               const int64_t o = (p0 + pl) * (int64_t)P.k + j;
-              P.D[o] = __builtin_fmaxf(nx[cb] - 2.0f * w[r], 0.0f);
-              if (P.flagged) P.flagged[o] = 0;
+              as_global(P.D)[o] = __builtin_fmaxf(nx[cb] - 2.0f * w[r], 0.0f);
+              if (P.flagged) as_global(P.flagged)[o] = 0;
             }
           }
         }
@@ -529,8 +529,8 @@ k_assign_mfma(const AssignProb* __restrict__ probs, const int32_t* __restrict__ 
       if (lab < 0 || lab >= P.k) lab = 0;  // only with non-finite data (status raised)
       const int64_t p = p0 + pl;
       const double dd = sqdist64(P.X + p * d, P.C + (int64_t)lab * d, d);
-      P.labels[p] = lab;
-      if (P.mindist) P.mindist[p] = (float)dd;
+      as_global(P.labels)[p] = lab;
+      if (P.mindist) as_global(P.mindist)[p] = (float)dd;
       sse += dd;
     }
   }
@@ -549,8 +549,8 @@ k_assign_mfma(const AssignProb* __restrict__ probs, const int32_t* __restrict__ 
       s += s_sse[w];
       c += s_corr[w];
     }
-    P.sse_part[tile] = s;
-    P.corr_part[tile] = c;
+    as_global(P.sse_part)[tile] = s;
+    as_global(P.corr_part)[tile] = c;
   }
 }
 
@@ -605,7 +605,7 @@ k_assign_pipe(const AssignProb* __restrict__ probs, const int32_t* __restrict__ 
   for (int cb = 0; cb < NB; ++cb) {
     const int pl = pw + cb * 32 + (lane & 31);
     const bool pv = pl < nvalid;
-    const float* xr = P.X + (p0 + (pv ? pl : 0)) * d;
+    const KM_GLOBAL float* xr = as_global(P.X) + (p0 + (pv ? pl : 0)) * d;
     float part = 0.0f;
 #pragma unroll
     for (int s = 0; s < Cfg::kSteps; ++s) {
@@ -615,7 +615,7 @@ k_assign_pipe(const AssignProb* __restrict__ probs, const int32_t* __restrict__ 
         if (fast) {
 #pragma unroll
           for (int u = 0; u < L::KV; u += 4) {
-            const f32x4 q = *reinterpret_cast<const f32x4*>(xr + o + u);
+            const f32x4 q = *reinterpret_cast<const KM_GLOBAL f32x4*>(xr + o + u);
             v[u] = q[0]; v[u + 1] = q[1]; v[u + 2] = q[2]; v[u + 3] = q[3];
           }
         } else {
@@ -683,12 +683,12 @@ k_assign_pipe(const AssignProb* __restrict__ probs, const int32_t* __restrict__ 
 
   const int kpad = P.k_pad;
   const int ntile = (kpad + CT - 1) / CT;
-  const S* Cq = reinterpret_cast<const S*>(P.Cq);
+  const KM_GLOBAL S* Cq = reinterpret_cast<const KM_GLOBAL S*>(as_global(P.Cq));
   f32x4 stage[Cfg::kChunksPerThread];
   float st_ci = 0.f, st_ca = 0.f;
   auto load_tile = [&](int t) {
     const int rows = (kpad - t * CT) < CT ? (kpad - t * CT) : CT;
-    const f32x4* g = reinterpret_cast<const f32x4*>(Cq + (int64_t)t * CT * DP);
+    const KM_GLOBAL f32x4* g = reinterpret_cast<const KM_GLOBAL f32x4*>(Cq + (int64_t)t * CT * DP);
     const int nchunk = rows * DP / Cfg::kElemsPerChunk;
 #pragma unroll
     for (int u = 0; u < Cfg::kChunksPerThread; ++u) {
@@ -696,8 +696,8 @@ k_assign_pipe(const AssignProb* __restrict__ probs, const int32_t* __restrict__ 
       if (c < nchunk) stage[u] = g[c];
     }
     if (tid < rows) {
-      st_ci = P.cinit[t * CT + tid];
-      st_ca = P.ca[t * CT + tid];
+      st_ci = as_global(P.cinit)[t * CT + tid];
+      st_ca = as_global(P.ca)[t * CT + tid];
     }
   };
   auto store_tile = [&](int t) {
@@ -912,7 +912,7 @@ k_assign_pipe(const AssignProb* __restrict__ probs, const int32_t* __restrict__ 
     int lab = bb[cb];
     if (cj[cb] >= 0 && (cd[cb] < dk || (cd[cb] == dk && cj[cb] < lab) || lab < 0)) lab = cj[cb];
     if (lab < 0 || lab >= P.k) lab = 0;  // only with non-finite data (status raised)
-    P.labels[p0 + pl] = lab;
+    as_global(P.labels)[p0 + pl] = lab;
     s_lab[wave][cb * 32 + (lane & 31)] = lab;
   }
   {
@@ -935,419 +935,8 @@ k_assign_pipe(const AssignProb* __restrict__ probs, const int32_t* __restrict__ 
       ssum += s_sse[w];
       c += s_corr[w];
     }
-    P.sse_part[tile] = ssum;
-    P.corr_part[tile] = c;
-  }
-}
-
-// ---------------------------------------------------------------------------
-// Fused mixed-precision assignment for the 16-bit formats (assignment mode),
-// one wave per SIMD.
-//
-// Same arithmetic as k_assign_pipe.  Schedule:
-//   * 4 waves x NB 32-point column blocks: each wave keeps the fragments of
-//     NB*32 points in registers, so each A fragment read from LDS feeds NB
-//     MFMAs.
-//   * Centre tiles (64 rows) live in a ring of three LDS slots.  Tile t+2 is
-//     fetched from global memory while tile t is processed and stored at the
-//     end of tile t, so the A fragments, accumulator starts and test constants
-//     of the next 32-centre block can always be read one step ahead: the
-//     barrier at the end of a tile never exposes an LDS read latency.
-//   * One accumulator per column block.  The MFMA chain of column block c is
-//     issued while the wave runs the epilogue of column block c-1 (and, for
-//     c = 0, of the last column block of the previous centre block), so the
-//     matrix core and the vector ALU work side by side in one wave.
-// ---------------------------------------------------------------------------
-template <class L, int DP>
-struct RingCfg {
-  static constexpr int kWaves = 4;
-  static constexpr int kThreads = 64 * kWaves;
-  static constexpr int NB = ring_nb(DP);
-  static constexpr int kPts = kWaves * NB * 32;
-  static constexpr int kCt = 64;                       // centres per tile
-  static constexpr int kSlots = 3;
-  static constexpr int kLd = DP + 8;                   // LDS row stride (elements)
-  static constexpr int kSteps = DP / L::KS;
-  static constexpr int kChunks = kCt * DP * 2 / 16;   // 16-byte chunks per tile
-  static constexpr int kChunksPerThread = (kChunks + kThreads - 1) / kThreads;
-  static constexpr int kCpr = DP * 2 / 16;             // chunks per centre row
-};
-
-template <class L, int DP, bool FALLBACK>
-__global__ void __launch_bounds__(256, 1)
-k_assign_ring(const AssignProb* __restrict__ probs, const int32_t* __restrict__ wg_start, int nprob) {
-  using Cfg = RingCfg<L, DP>;
-  using S = typename L::S;
-  using F = typename L::frag;
-  constexpr int NB = Cfg::NB;
-  constexpr int NT = Cfg::kThreads;
-  constexpr int CT = Cfg::kCt;
-  constexpr int LD = Cfg::kLd;
-  constexpr int KST = Cfg::kSteps;
-  constexpr int kQueue = 8;
-  static_assert(L::KS == 16 && L::KV == 8, "16-bit formats only");
-
-  __shared__ __attribute__((aligned(16))) S s_c[Cfg::kSlots * CT * LD];
-  __shared__ __attribute__((aligned(16))) float s_ci[Cfg::kSlots][CT];
-  __shared__ __attribute__((aligned(16))) float s_ca[Cfg::kSlots][CT];
-  __shared__ f32x4 s_sv[Cfg::kWaves][NB][4][64];  // saved best block: [wave][cb][r/4][lane]
-  __shared__ int s_q[FALLBACK ? kQueue * NT : 1];
-  __shared__ int s_lab[Cfg::kWaves][NB * 32];
-  __shared__ double s_sse[Cfg::kWaves];
-  __shared__ unsigned long long s_corr[Cfg::kWaves];
-
-  const int tid = threadIdx.x;
-  const int lane = tid & 63;
-  const int wave = tid >> 6;
-  const int pi = find_problem(wg_start, nprob, blockIdx.x);
-  const AssignProb& P = probs[pi];
-  const int tile = blockIdx.x - wg_start[pi];
-  const int64_t p0 = (int64_t)tile * Cfg::kPts;
-  const int64_t n = P.n;
-  const int d = P.d;
-  const int nvalid = (int)((n - p0) < Cfg::kPts ? (n - p0) : Cfg::kPts);
-
-  // ---- prologue: point fragments (RNE low precision) and quantised norms
-  F bfr[NB][KST];
-  float nx[NB], hx[NB];
-  const int pw = wave * NB * 32;
-  int bad = 0;
-  // rows past the end read row 0 of the tile and are zeroed; coordinates
-  // past d read coordinate d-1 and are zeroed (no divergent loads)
-  const bool fast = ((((uintptr_t)P.X) & 15) == 0) && d == DP;
-#pragma unroll
-  for (int cb = 0; cb < NB; ++cb) {
-    const int pl = pw + cb * 32 + (lane & 31);
-    const bool pv = pl < nvalid;
-    const float* xr = P.X + (p0 + (pv ? pl : 0)) * d;
-    float part = 0.0f;
-#pragma unroll
-    for (int s = 0; s < KST; ++s) {
-      const int o = s * L::KS + (lane >> 5) * L::KV;
-      float v[L::KV];
-      if (fast) {
-#pragma unroll
-        for (int u = 0; u < L::KV; u += 4) {
-          const f32x4 q = *reinterpret_cast<const f32x4*>(xr + o + u);
-          v[u] = pv ? q[0] : 0.0f;
-          v[u + 1] = pv ? q[1] : 0.0f;
-          v[u + 2] = pv ? q[2] : 0.0f;
-          v[u + 3] = pv ? q[3] : 0.0f;
-        }
-      } else {
-#pragma unroll
-        for (int u = 0; u < L::KV; ++u) {
-          const int l = o + u;
-          const float x = xr[l < d ? l : d - 1];
-          v[u] = (pv && l < d) ? x : 0.0f;
-        }
-      }
-      F f;
-#pragma unroll
-      for (int u = 0; u < L::KV; ++u) {
-        if (!__builtin_isfinite(v[u])) bad |= kStatusNonFinite;
-        if (L::kHasRange && __builtin_fabsf(v[u]) >= L::kOverflow) bad |= kStatusRange;
-        const S q = L::cvt(v[u]);
-        f[u] = q;
-        const float qf = L::tof(q);
-        part = __builtin_fmaf(qf, qf, part);
-      }
-      bfr[cb][s] = f;
-      // the point fragments are only ever MFMA operands: keep them in the
-      // accumulation register file and leave the architectural VGPRs to the
-      // accumulators and the epilogue
-      asm volatile("" : "+a"(bfr[cb][s]));
-    }
-    const float other = __shfl_xor(part, 32, kWave);
-    nx[cb] = (lane < 32) ? part + other : other + part;
-    hx[cb] = pv ? 0.5f * (P.oma * nx[cb]) : __builtin_inff();
-  }
-  raise_status(P.status, bad);
-
-  float bw[NB];
-  int bb[NB];
-  float cd[NB];
-  int cj[NB];
-#pragma unroll
-  for (int cb = 0; cb < NB; ++cb) {
-    bw[cb] = -__builtin_inff();
-    bb[cb] = -1;
-    cd[cb] = __builtin_inff();
-    cj[cb] = -1;
-  }
-  unsigned long long ncorr = 0;
-  int qn = 0;
-  auto flush_queue = [&]() {
-    if constexpr (FALLBACK) {
-      for (int q = 0; q < qn; ++q) {
-        const int e = s_q[q * NT + tid];
-        const int j = e & 0xffffff;
-        const int cbq = e >> 24;
-        const int pl = pw + cbq * 32 + (lane & 31);
-        const float df = (float)sqdist64_call(P.X + (p0 + pl) * d, P.C + (int64_t)j * d, d);
-        ncorr += 1;
-#pragma unroll
-        for (int cb = 0; cb < NB; ++cb) {
-          if (cb != cbq) continue;
-          if (df < cd[cb] || (df == cd[cb] && j < cj[cb])) {
-            cd[cb] = df;
-            cj[cb] = j;
-          }
-        }
-      }
-      qn = 0;
-    }
-  };
-
-  // ---- centre tiles: global -> registers -> LDS ring slot
-  const int kpad = P.k_pad;
-  const int ntile = (kpad + CT - 1) / CT;
-  const int nblk = kpad / 32;
-  const S* Cq = reinterpret_cast<const S*>(P.Cq);
-  f32x4 stage[Cfg::kChunksPerThread];
-  float st_ci = 0.f, st_ca = 0.f;
-  auto load_tile = [&](int t) {
-    const int rows = (kpad - t * CT) < CT ? (kpad - t * CT) : CT;
-    const f32x4* g = reinterpret_cast<const f32x4*>(Cq + (int64_t)t * CT * DP);
-    const int nchunk = rows * Cfg::kCpr;
-#pragma unroll
-    for (int u = 0; u < Cfg::kChunksPerThread; ++u) {
-      const int c = tid + u * NT;
-      if (c < nchunk) stage[u] = g[c];
-    }
-    if (tid < rows) {
-      st_ci = P.cinit[t * CT + tid];
-      st_ca = P.ca[t * CT + tid];
-    }
-  };
-  auto store_tile = [&](int t) {
-    const int rows = (kpad - t * CT) < CT ? (kpad - t * CT) : CT;
-    const int nchunk = rows * Cfg::kCpr;
-    S* dst = s_c + (t % Cfg::kSlots) * CT * LD;
-#pragma unroll
-    for (int u = 0; u < Cfg::kChunksPerThread; ++u) {
-      const int c = tid + u * NT;
-      if (c < nchunk) {
-        const int row = c / Cfg::kCpr, col = (c % Cfg::kCpr) * 8;
-        *reinterpret_cast<f32x4*>(dst + row * LD + col) = stage[u];
-      }
-    }
-    if (tid < rows) {
-      s_ci[t % Cfg::kSlots][tid] = st_ci;
-      s_ca[t % Cfg::kSlots][tid] = st_ca;
-    }
-  };
-
-  // LDS addresses of a 32-centre block b (tile b/2, rows 32*(b%2) ...)
-  auto arow = [&](int b) -> const S* {
-    return s_c + ((b >> 1) % Cfg::kSlots) * CT * LD + ((b & 1) * 32 + (lane & 31)) * LD + (lane >> 5) * L::KV;
-  };
-  // the 16 rows of a block held by this lane's accumulator registers
-  auto load_rows = [&](const float (*tab)[CT], int b, f32x16& v) {
-    const float* base = &tab[(b >> 1) % Cfg::kSlots][(b & 1) * 32 + 4 * (lane >> 5)];
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const f32x4 w = *reinterpret_cast<const f32x4*>(base + 8 * q);
-      v[4 * q] = w[0]; v[4 * q + 1] = w[1]; v[4 * q + 2] = w[2]; v[4 * q + 3] = w[3];
-    }
-  };
-
-  f32x16 acc[NB];
-  F af[KST];
-  // two register sets (even / odd centre blocks) of accumulator starts and
-  // test constants, so the next block's values load while the current ones
-  // are still in use
-  f32x16 ciA, ciB, cavA, cavB;
-
-  // epilogue of column block c for centre block b (accumulator acc[c],
-  // test constants cav): reliability test, rare slow path for flagged pairs,
-  // running best with the saved block in LDS
-  auto epilogue = [&](int c, int b, const f32x16& cav) {
-    const int jb = b * 32;
-    float wm = max16(acc[c]);
-    if constexpr (FALLBACK) {
-      const float tm = max16(acc[c] + cav);
-      if (__builtin_expect(__ballot(tm >= hx[c]) != 0, 0)) {  // rare, wave-uniform
-        const int pl = pw + c * 32 + (lane & 31);
-        f32x16 w = acc[c];
-        uint32_t fm = 0;
-#pragma unroll
-        for (int r = 0; r < 16; ++r) {
-          const bool f = w[r] + cav[r] >= hx[c];
-          fm |= (uint32_t)f << r;
-          w[r] = f ? -__builtin_inff() : w[r];
-        }
-        wm = max16(w);
-        if (pl >= nvalid) fm = 0;
-        while (fm) {
-          const int r = __builtin_ctz(fm);
-          fm &= fm - 1;
-          const int j = jb + acc_row(r, lane);
-          if (j >= P.k) continue;
-          if (qn < kQueue) {
-            s_q[qn * NT + tid] = j | (c << 24);
-            qn += 1;
-          } else {  // queue full (dense flags): correct this pair now
-            const float df = (float)sqdist64_call(P.X + (p0 + pl) * d, P.C + (int64_t)j * d, d);
-            ncorr += 1;
-            if (df < cd[c] || (df == cd[c] && j < cj[c])) {
-              cd[c] = df;
-              cj[c] = j;
-            }
-          }
-        }
-        if (wm > bw[c]) {
-          bw[c] = wm;
-          bb[c] = jb;
-#pragma unroll
-          for (int q = 0; q < 4; ++q) {
-            f32x4 v = {w[4 * q], w[4 * q + 1], w[4 * q + 2], w[4 * q + 3]};
-            s_sv[wave][c][q][lane] = v;
-          }
-        }
-        return;
-      }
-    }
-    if (wm > bw[c]) {  // strict: the earlier block keeps ties
-      bw[c] = wm;
-      bb[c] = jb;
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        f32x4 v = {acc[c][4 * q], acc[c][4 * q + 1], acc[c][4 * q + 2], acc[c][4 * q + 3]};
-        s_sv[wave][c][q][lane] = v;
-      }
-    }
-  };
-
-  // one centre block b: MFMA chains of the NB column blocks, each beside the
-  // epilogue of the column block before it; the fragments and constants of
-  // block b+1 are read from LDS on the way
-  auto do_block = [&](int b, const f32x16& ciC, f32x16& ciN, const f32x16& cavC, f32x16& cavO) {
-    const int bn = (b + 1 < nblk) ? b + 1 : b;
-    const S* an = arow(bn);
-#pragma unroll
-    for (int c = 0; c < NB; ++c) {
-#pragma unroll
-      for (int s = 0; s < KST; ++s) {
-        acc[c] = L::mfma(af[s], bfr[c][s], s == 0 ? ciC : acc[c]);
-        if (c == NB - 1) af[s] = *reinterpret_cast<const F*>(an + s * L::KS);
-      }
-      if (c == 0) {
-        epilogue(NB - 1, b - 1, cavO);  // no-op for b = 0 (accumulator at -inf)
-        load_rows(s_ci, bn, ciN);
-        load_rows(s_ca, bn, cavO);
-      } else {
-        epilogue(c - 1, b, cavC);
-      }
-    }
-  };
-  auto tile_end = [&](int b) {
-    const int t = b >> 1;
-    if (t + 2 < ntile) store_tile(t + 2);
-    if constexpr (FALLBACK) {
-      if (__ballot(qn >= kQueue / 2)) flush_queue();  // batch: rare flags wait to the end
-    }
-    __syncthreads();
-    if (t + 3 < ntile) load_tile(t + 3);
-  };
-
-  // prologue of the sweep: tiles 0 and 1 in LDS, tile 2 in flight
-  load_tile(0);
-  store_tile(0);
-  if (ntile > 1) {
-    load_tile(1);
-    store_tile(1);
-  }
-  __syncthreads();
-  if (ntile > 2) load_tile(2);
-  {
-    const S* a0 = arow(0);
-#pragma unroll
-    for (int s = 0; s < KST; ++s) af[s] = *reinterpret_cast<const F*>(a0 + s * L::KS);
-  }
-  load_rows(s_ci, 0, ciA);
-  load_rows(s_ca, 0, cavA);
-#pragma unroll
-  for (int r = 0; r < 16; ++r) {
-    acc[NB - 1][r] = -__builtin_inff();
-    cavB[r] = 0.0f;
-  }
-
-  for (int b = 0; b < nblk; b += 2) {
-    do_block(b, ciA, ciB, cavA, cavB);
-    if (b + 1 == nblk) {
-      tile_end(b);
-      break;
-    }
-    do_block(b + 1, ciB, ciA, cavB, cavA);
-    tile_end(b + 1);
-  }
-  epilogue(NB - 1, nblk - 1, (nblk & 1) ? cavA : cavB);
-  flush_queue();
-
-  // ---- index of the best kept pair, merge the two lanes that share a
-  // point, choose between kept and corrected, refine in FP64
-  double sse = 0.0;
-#pragma unroll
-  for (int cb = 0; cb < NB; ++cb) {
-    int rs = 16;
-    if (bb[cb] >= 0) {
-#pragma unroll
-      for (int q = 3; q >= 0; --q) {
-        const f32x4 v = s_sv[wave][cb][q][lane];
-#pragma unroll
-        for (int e = 3; e >= 0; --e) rs = (v[e] == bw[cb]) ? 4 * q + e : rs;
-      }
-    }
-    int bj = (bb[cb] >= 0 && rs < 16) ? bb[cb] + acc_row(rs, lane) : -1;
-    float ow = __shfl_xor(bw[cb], 32, kWave);
-    int oj = __shfl_xor(bj, 32, kWave);
-    if (ow > bw[cb] || (ow == bw[cb] && oj >= 0 && (bj < 0 || oj < bj))) {
-      bw[cb] = ow;
-      bj = oj;
-    }
-    float od = __shfl_xor(cd[cb], 32, kWave);
-    int ojc = __shfl_xor(cj[cb], 32, kWave);
-    if (od < cd[cb] || (od == cd[cb] && ojc >= 0 && (cj[cb] < 0 || ojc < cj[cb]))) {
-      cd[cb] = od;
-      cj[cb] = ojc;
-    }
-    bb[cb] = bj;
-  }
-#pragma unroll
-  for (int cb = 0; cb < NB; ++cb) {
-    if ((cb & 1) != (lane >> 5)) continue;
-    const int pl = pw + cb * 32 + (lane & 31);
-    if (pl >= nvalid) continue;
-    const float dk = bb[cb] >= 0 ? __builtin_fmaxf(nx[cb] - 2.0f * bw[cb], 0.0f) : __builtin_inff();
-    int lab = bb[cb];
-    if (cj[cb] >= 0 && (cd[cb] < dk || (cd[cb] == dk && cj[cb] < lab) || lab < 0)) lab = cj[cb];
-    if (lab < 0 || lab >= P.k) lab = 0;  // only with non-finite data (status raised)
-    P.labels[p0 + pl] = lab;
-    s_lab[wave][cb * 32 + (lane & 31)] = lab;
-  }
-  {
-    int nloc = nvalid - pw;
-    nloc = nloc < 0 ? 0 : (nloc > NB * 32 ? NB * 32 : nloc);
-    sse = refine_wave(P, p0 + pw, nloc, s_lab[wave], lane);
-  }
-  sse = wave_sum(sse);
-  unsigned long long nc = wave_sum_u64(ncorr);
-  if (lane == 0) {
-    s_sse[wave] = sse;
-    s_corr[wave] = nc;
-  }
-  __syncthreads();
-  if (tid == 0) {
-    double ssum = 0.0;
-    unsigned long long c = 0;
-#pragma unroll
-    for (int w = 0; w < Cfg::kWaves; ++w) {
-      ssum += s_sse[w];
-      c += s_corr[w];
-    }
-    P.sse_part[tile] = ssum;
-    P.corr_part[tile] = c;
+    as_global(P.sse_part)[tile] = ssum;
+    as_global(P.corr_part)[tile] = c;
   }
 }
 
@@ -1397,14 +986,14 @@ k_assign_direct64(const AssignProb* __restrict__ probs, const int32_t* __restric
         const int p = e / DC, l = e % DC;
         float v = 0.f;
         if (p < nvalid && l0 + l < d) {
-          v = P.X[(p0 + p) * d + l0 + l];
+          v = as_global(P.X)[(p0 + p) * d + l0 + l];
           if (c0 == 0) {
             if (!__builtin_isfinite(v)) bad |= kStatusNonFinite;
           }
         }
         sxs[p][l] = v;
         float w = 0.f;
-        if (c0 + p < k && l0 + l < d) w = P.C[(int64_t)(c0 + p) * d + l0 + l];
+        if (c0 + p < k && l0 + l < d) w = as_global(P.C)[(int64_t)(c0 + p) * d + l0 + l];
         scs[p][l] = w;
       }
       __syncthreads();
@@ -1439,8 +1028,8 @@ k_assign_direct64(const AssignProb* __restrict__ probs, const int32_t* __restric
             }
           } else {
             const int64_t o = (p0 + p) * (int64_t)k + j;
-            P.D[o] = (float)acc[a][b];
-            if (P.flagged) P.flagged[o] = 1;
+            as_global(P.D)[o] = (float)acc[a][b];
+            if (P.flagged) as_global(P.flagged)[o] = 1;
           }
         }
       }
@@ -1469,8 +1058,8 @@ k_assign_direct64(const AssignProb* __restrict__ probs, const int32_t* __restric
       const int64_t p = p0 + tid;
       if (bi < 0) bi = 0;  // only with non-finite data (status raised)
       const double dd = sqdist64(P.X + p * d, P.C + (int64_t)bi * d, d);
-      P.labels[p] = bi;
-      if (P.mindist) P.mindist[p] = (float)dd;
+      as_global(P.labels)[p] = bi;
+      if (P.mindist) as_global(P.mindist)[p] = (float)dd;
       sse = dd;
     }
   }
@@ -1483,8 +1072,8 @@ k_assign_direct64(const AssignProb* __restrict__ probs, const int32_t* __restric
   }
   __syncthreads();
   if (tid == 0) {
-    P.sse_part[tile] = s_sse[0] + s_sse[1] + s_sse[2] + s_sse[3];
-    P.corr_part[tile] = s_corr[0] + s_corr[1] + s_corr[2] + s_corr[3];
+    as_global(P.sse_part)[tile] = s_sse[0] + s_sse[1] + s_sse[2] + s_sse[3];
+    as_global(P.corr_part)[tile] = s_corr[0] + s_corr[1] + s_corr[2] + s_corr[3];
   }
 }
 
@@ -1502,8 +1091,8 @@ k_reduce_parts(const ReduceProb* __restrict__ probs) {
   double s = 0.0;
   unsigned long long c = 0;
   for (int i = tid; i < P.nparts; i += 256) {
-    s += P.sse_part[i];
-    c += P.corr_part[i];
+    s += as_global(P.sse_part)[i];
+    c += as_global(P.corr_part)[i];
   }
   ss[tid] = s;
   sc[tid] = c;
@@ -1555,15 +1144,6 @@ hipError_t launch_prep(int low, const PrepProb* dprobs, const int32_t* dstart, i
 template <class L, int DP, int NB>
 static hipError_t launch_mfma_t(int mode, bool fallback, const AssignProb* dprobs, const int32_t* dstart,
                                 int nprob, int nwg, hipStream_t st) {
-  if constexpr (uses_ring(L::KS == 16 ? kLowFP16 : kLowFP32, DP)) {
-    if (mode == 0) {
-      if (fallback)
-        hipLaunchKernelGGL((k_assign_ring<L, DP, true>), dim3(nwg), dim3(256), 0, st, dprobs, dstart, nprob);
-      else
-        hipLaunchKernelGGL((k_assign_ring<L, DP, false>), dim3(nwg), dim3(256), 0, st, dprobs, dstart, nprob);
-      return hipGetLastError();
-    }
-  }
   if (mode == 0) {
     if (fallback)
       hipLaunchKernelGGL((k_assign_pipe<L, DP, NB, true>), dim3(nwg), dim3(kPipeThreads), 0, st, dprobs, dstart, nprob);

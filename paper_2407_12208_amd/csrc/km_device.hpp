@@ -15,6 +15,21 @@ typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 
 constexpr int kWave = 64;
 
+// Pointers to device memory held in problem descriptors are generic (flat)
+// pointers.  Flat loads count against the LDS wait counter as well, so an LDS
+// wait would also wait for every outstanding flat load: a prefetch from
+// global memory would complete before the next LDS read could be used.
+// Kernels therefore access device memory through global-address-space views.
+#define KM_GLOBAL __attribute__((address_space(1)))
+template <class T>
+__device__ __forceinline__ const KM_GLOBAL T* as_global(const T* p) {
+  return (const KM_GLOBAL T*)p;
+}
+template <class T>
+__device__ __forceinline__ KM_GLOBAL T* as_global(T* p) {
+  return (KM_GLOBAL T*)p;
+}
+
 
 // ---------------------------------------------------------------------------
 // Low-precision formats.  Each provides: the storage type S; the matrix-core
@@ -80,14 +95,16 @@ __device__ __host__ constexpr int acc_row(int r, int lane) {
 // Direct formula eq:dist-direct in FP64 from FP32 data: differences and the
 // running sum in FP64, coordinates in index order (fused multiply-add).
 // ---------------------------------------------------------------------------
-__device__ inline double sqdist64(const float* __restrict__ x,
-                                  const float* __restrict__ c, int d) {
+__device__ inline double sqdist64(const float* __restrict__ xp,
+                                  const float* __restrict__ cp, int d) {
+  const KM_GLOBAL float* x = as_global(xp);
+  const KM_GLOBAL float* c = as_global(cp);
   double s = 0.0;
   int l = 0;
-  if ((((uintptr_t)x | (uintptr_t)c) & 15) == 0 && (d & 3) == 0) {
+  if ((((uintptr_t)xp | (uintptr_t)cp) & 15) == 0 && (d & 3) == 0) {
     for (; l < d; l += 4) {
-      float4 a = *reinterpret_cast<const float4*>(x + l);
-      float4 b = *reinterpret_cast<const float4*>(c + l);
+      f32x4 a = *reinterpret_cast<const KM_GLOBAL f32x4*>(x + l);
+      f32x4 b = *reinterpret_cast<const KM_GLOBAL f32x4*>(c + l);
       double e0 = (double)a.x - (double)b.x;
       double e1 = (double)a.y - (double)b.y;
       double e2 = (double)a.z - (double)b.z;

@@ -34,14 +34,8 @@ constexpr int mfma_points_per_wg(int low, int DP) { return 4 * 32 * mfma_nb(low,
 constexpr int kPipeWaves = 8;
 constexpr int kPipeThreads = 64 * kPipeWaves;
 constexpr int pipe_points_per_wg(int low, int DP) { return kPipeWaves * 32 * mfma_nb(low, DP); }
-// one-wave-per-SIMD assignment kernel (16-bit formats, DP <= 128): 4 waves of
-// ring_nb(DP) 32-point column blocks
-constexpr bool uses_ring(int low, int DP) { return low != kLowFP32 && DP <= 128; }
-constexpr int ring_nb(int DP) { return DP <= 128 ? 4 : 2; }
 // points per workgroup of the assignment-mode kernel
-constexpr int assign_points_per_wg(int low, int DP) {
-  return uses_ring(low, DP) ? 4 * 32 * ring_nb(DP) : pipe_points_per_wg(low, DP);
-}
+constexpr int assign_points_per_wg(int low, int DP) { return pipe_points_per_wg(low, DP); }
 constexpr int kDirectPointsPerWg = 64;
 
 // Accumulated per-problem results on the device.

@@ -51,12 +51,12 @@ k_upd_hist(const UpdateProb* __restrict__ probs, const int32_t* __restrict__ wg_
     for (int j = threadIdx.x; j < sl; j += 256) cnt[j] = 0;
     __syncthreads();
     for (int i = threadIdx.x; i < m; i += 256) {
-      const int lab = P.labels[p0 + i];
+      const int lab = as_global(P.labels)[p0 + i];
       if (lab < 0 || lab >= P.k) bad = 1;
       else if (lab >= s0 && lab < s0 + sl) atomicAdd(&cnt[lab - s0], 1);
     }
     __syncthreads();
-    for (int j = threadIdx.x; j < sl; j += 256) P.hist[(int64_t)(s0 + j) * P.ntiles + tile] = cnt[j];
+    for (int j = threadIdx.x; j < sl; j += 256) as_global(P.hist)[(int64_t)(s0 + j) * P.ntiles + tile] = cnt[j];
     __syncthreads();
   }
   if (bad) atomicOr(P.status, kStatusBadLabel);
@@ -72,8 +72,8 @@ k_upd_scan_rel(const UpdateProb* __restrict__ probs, const int32_t* __restrict__
   const int T = P.ntiles;
   const int per = (T + 255) / 256;
   const int t0 = threadIdx.x * per;
-  const int32_t* h = P.hist + (int64_t)j * T;
-  int32_t* o = P.offs + (int64_t)j * T;
+  const KM_GLOBAL int32_t* h = as_global(P.hist) + (int64_t)j * T;
+  KM_GLOBAL int32_t* o = as_global(P.offs) + (int64_t)j * T;
   int s = 0;
   for (int t = t0; t < t0 + per && t < T; ++t) s += h[t];
   part[threadIdx.x] = s;
@@ -90,7 +90,7 @@ k_upd_scan_rel(const UpdateProb* __restrict__ probs, const int32_t* __restrict__
     o[t] = run;
     run += h[t];
   }
-  if (threadIdx.x == 255) P.cstart[j] = part[255];  // count, scanned by k_upd_scan_cl
+  if (threadIdx.x == 255) as_global(P.cstart)[j] = part[255];  // count, scanned by k_upd_scan_cl
 }
 
 // 3. per problem: counts -> exclusive cluster starts and chunk starts
@@ -108,7 +108,7 @@ k_upd_scan_cl(const UpdateProb* __restrict__ probs) {
   __syncthreads();
   for (int base = 0; base < P.k; base += 1024) {
     const int j = base + tid;
-    const int mj = j < P.k ? P.cstart[j] : 0;
+    const int mj = j < P.k ? as_global(P.cstart)[j] : 0;
     const int cj = (mj + kUpdChunk - 1) / kUpdChunk;
     a[tid] = mj;
     b[tid] = cj;
@@ -123,8 +123,8 @@ k_upd_scan_cl(const UpdateProb* __restrict__ probs) {
     }
     const int c0 = carry[0], c1 = carry[1];
     if (j < P.k) {
-      P.cstart[j] = c0 + a[tid] - mj;
-      P.chunk_start[j] = c1 + b[tid] - cj;
+      as_global(P.cstart)[j] = c0 + a[tid] - mj;
+      as_global(P.chunk_start)[j] = c1 + b[tid] - cj;
     }
     __syncthreads();
     if (tid == 1023) {
@@ -134,8 +134,8 @@ k_upd_scan_cl(const UpdateProb* __restrict__ probs) {
     __syncthreads();
   }
   if (tid == 0) {
-    P.cstart[P.k] = carry[0];
-    P.chunk_start[P.k] = carry[1];
+    as_global(P.cstart)[P.k] = carry[0];
+    as_global(P.chunk_start)[P.k] = carry[1];
   }
 }
 
@@ -162,13 +162,13 @@ k_upd_scatter(const UpdateProb* __restrict__ probs, const int32_t* __restrict__ 
   if (P.k <= kScatterLds) {
     int* c = cnt[wave];
     // running output position of each cluster for this tile
-    for (int j = lane; j < P.k; j += 64) c[j] = P.cstart[j] + P.offs[(int64_t)j * P.ntiles + tile];
+    for (int j = lane; j < P.k; j += 64) c[j] = as_global(P.cstart)[j] + as_global(P.offs)[(int64_t)j * P.ntiles + tile];
     int nbits = 0;
     while ((1 << nbits) < P.k) ++nbits;
     const unsigned long long below = (1ull << lane) - 1;
     for (int r0 = 0; r0 < m; r0 += 64) {
       const int i = r0 + lane;
-      const int lab = i < m ? P.labels[p0 + i] : -1;
+      const int lab = i < m ? as_global(P.labels)[p0 + i] : -1;
       const bool ok = lab >= 0 && lab < P.k;
       unsigned long long grp = __ballot(ok);
       for (int b = 0; b < nbits; ++b) {
@@ -180,7 +180,7 @@ k_upd_scatter(const UpdateProb* __restrict__ probs, const int32_t* __restrict__ 
       // included when ok)
       if (ok) {
         const int base = c[lab];
-        P.perm[base + __popcll(grp & below)] = (int32_t)(p0 + i);
+        as_global(P.perm)[base + __popcll(grp & below)] = (int32_t)(p0 + i);
       }
       // every lane of the round has read its counter above before any
       // group leader writes it (the wave executes the reads first)
@@ -188,12 +188,12 @@ k_upd_scatter(const UpdateProb* __restrict__ probs, const int32_t* __restrict__ 
     }
   } else {
     for (int i = lane; i < m; i += 64) {
-      const int lab = P.labels[p0 + i];
+      const int lab = as_global(P.labels)[p0 + i];
       if (lab < 0 || lab >= P.k) continue;
       int rank = 0;
-      for (int q = 0; q < i; ++q) rank += (P.labels[p0 + q] == lab);
-      const int pos = P.cstart[lab] + P.offs[(int64_t)lab * P.ntiles + tile] + rank;
-      P.perm[pos] = (int32_t)(p0 + i);
+      for (int q = 0; q < i; ++q) rank += (as_global(P.labels)[p0 + q] == lab);
+      const int pos = as_global(P.cstart)[lab] + as_global(P.offs)[(int64_t)lab * P.ntiles + tile] + rank;
+      as_global(P.perm)[pos] = (int32_t)(p0 + i);
     }
   }
 }
@@ -222,7 +222,7 @@ __device__ inline void chunk_rows(const UpdateProb& P, int c, int m0, int m1, in
   for (int q = 0; q < kMaxSlots; ++q)
 #pragma unroll
     for (int e = 0; e < 4; ++e) s[q][e] = 0.0;
-  const float* __restrict__ X = P.X;
+  const KM_GLOBAL float* __restrict__ X = as_global(P.X);
   auto add_row = [&](int id) {
 #pragma unroll
     for (int q = 0; q < kMaxSlots; ++q) {
@@ -230,7 +230,7 @@ __device__ inline void chunk_rows(const UpdateProb& P, int c, int m0, int m1, in
       const int v = cl + 64 * q;
       if (v >= nv) continue;
       if constexpr (VEC) {
-        const float4 x = *reinterpret_cast<const float4*>(X + (int64_t)id * d + 4 * v);
+        const f32x4 x = *reinterpret_cast<const KM_GLOBAL f32x4*>(X + (int64_t)id * d + 4 * v);
         s[q][0] += (double)x.x;
         s[q][1] += (double)x.y;
         s[q][2] += (double)x.z;
@@ -245,14 +245,14 @@ __device__ inline void chunk_rows(const UpdateProb& P, int c, int m0, int m1, in
   for (; mm + 7 * G < m1; mm += 8 * G) {
     int idx[8];
 #pragma unroll
-    for (int u = 0; u < 8; ++u) idx[u] = P.perm[mm + u * G];
+    for (int u = 0; u < 8; ++u) idx[u] = as_global(P.perm)[mm + u * G];
     if constexpr (VEC) {
-      float4 xv[8];
+      f32x4 xv[8];
       const int v = cl;
       const bool on = v < nv;
 #pragma unroll
       for (int u = 0; u < 8; ++u)
-        xv[u] = on ? *reinterpret_cast<const float4*>(X + (int64_t)idx[u] * d + 4 * v) : make_float4(0.f, 0.f, 0.f, 0.f);
+        xv[u] = on ? *reinterpret_cast<const KM_GLOBAL f32x4*>(X + (int64_t)idx[u] * d + 4 * v) : f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
       for (int u = 0; u < 8; ++u) {
         s[0][0] += (double)xv[u].x;
@@ -265,7 +265,7 @@ __device__ inline void chunk_rows(const UpdateProb& P, int c, int m0, int m1, in
       for (int u = 0; u < 8; ++u) add_row(idx[u]);
     }
   }
-  for (; mm < m1; mm += G) add_row(P.perm[mm]);
+  for (; mm < m1; mm += G) add_row(as_global(P.perm)[mm]);
   // combine the G groups (fixed butterfly over the group bits)
   for (int o = L; o < 64; o <<= 1) {
 #pragma unroll
@@ -282,7 +282,7 @@ __device__ inline void chunk_rows(const UpdateProb& P, int c, int m0, int m1, in
 #pragma unroll
       for (int e = 0; e < per; ++e) {
         const int l = per * v + e;
-        if (l < d) P.chunk_sum[(int64_t)c * d + l] = s[q][e];
+        if (l < d) as_global(P.chunk_sum)[(int64_t)c * d + l] = s[q][e];
       }
     }
   }
@@ -294,16 +294,16 @@ k_upd_chunksum(const UpdateProb* __restrict__ probs, const int32_t* __restrict__
   const UpdateProb& P = probs[pi];
   const int c = (blockIdx.x - wg_start[pi]) * 4 + (threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
-  if (c >= P.chunk_start[P.k]) return;
+  if (c >= as_global(P.chunk_start)[P.k]) return;
   // cluster owning chunk c
   int lo = 0, hi = P.k - 1;
   while (lo < hi) {
     int mid = (lo + hi + 1) >> 1;
-    if (P.chunk_start[mid] <= c) lo = mid; else hi = mid - 1;
+    if (as_global(P.chunk_start)[mid] <= c) lo = mid; else hi = mid - 1;
   }
   const int j = lo;
-  const int m0 = P.cstart[j] + (c - P.chunk_start[j]) * kUpdChunk;
-  const int m1 = (m0 + kUpdChunk) < P.cstart[j + 1] ? (m0 + kUpdChunk) : P.cstart[j + 1];
+  const int m0 = as_global(P.cstart)[j] + (c - as_global(P.chunk_start)[j]) * kUpdChunk;
+  const int m1 = (m0 + kUpdChunk) < as_global(P.cstart)[j + 1] ? (m0 + kUpdChunk) : as_global(P.cstart)[j + 1];
   if ((P.d & 3) == 0 && (((uintptr_t)P.X) & 15) == 0)
     chunk_rows<true>(P, c, m0, m1, lane);
   else
@@ -318,29 +318,29 @@ k_upd_finalize(const UpdateProb* __restrict__ probs, const int32_t* __restrict__
   const int j = (blockIdx.x - wg_start[pi]) * 4 + (threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   if (j >= P.k) return;
-  const int mj = P.cstart[j + 1] - P.cstart[j];
-  const int c0 = P.chunk_start[j], c1 = P.chunk_start[j + 1];
+  const int mj = as_global(P.cstart)[j + 1] - as_global(P.cstart)[j];
+  const int c0 = as_global(P.chunk_start)[j], c1 = as_global(P.chunk_start)[j + 1];
   const int d = P.d;
   double mv2 = 0.0;
   for (int l0 = 0; l0 < d; l0 += 64) {
     const int l = l0 + lane;
     if (l < d) {
-      const float old = P.C_old[(int64_t)j * d + l];
+      const float old = as_global(P.C_old)[(int64_t)j * d + l];
       float nv = old;
       if (mj > 0) {
         double s = 0.0;
-        for (int c = c0; c < c1; ++c) s += P.chunk_sum[(int64_t)c * d + l];
+        for (int c = c0; c < c1; ++c) s += as_global(P.chunk_sum)[(int64_t)c * d + l];
         nv = (float)(s / (double)mj);
       }
-      P.C_new[(int64_t)j * d + l] = nv;
+      as_global(P.C_new)[(int64_t)j * d + l] = nv;
       const double df = (double)nv - (double)old;
       mv2 += df * df;
     }
   }
   mv2 = wave_sum(mv2);
   if (lane == 0) {
-    P.shift2[j] = mv2;
-    if (P.counts_out) P.counts_out[j] = mj;
+    as_global(P.shift2)[j] = mv2;
+    if (P.counts_out) as_global(P.counts_out)[j] = mj;
   }
 }
 
@@ -350,7 +350,7 @@ k_upd_shift(const UpdateProb* __restrict__ probs) {
   __shared__ double mx[256];
   const UpdateProb& P = probs[blockIdx.x];
   double v = 0.0;
-  for (int j = threadIdx.x; j < P.k; j += 256) v = __builtin_fmax(v, P.shift2[j]);
+  for (int j = threadIdx.x; j < P.k; j += 256) v = __builtin_fmax(v, as_global(P.shift2)[j]);
   mx[threadIdx.x] = v;
   __syncthreads();
   for (int o = 128; o >= 1; o >>= 1) {
