@@ -5,9 +5,10 @@ Workload: the distance-kernel benchmark shape -- X 1,000,000 x 128 and C
 4,096 x 128, FP32 entries N(0,1) -- with the FP16 -> FP64 mixed-precision
 assignment (threshold rho~ = 5, equation form).  One step is one Lloyd round
 over that input: the fused assignment pass (range check, quantisation, norms,
-MFMA cross term, reliability test, FP64 correction, argmin, FP64 refinement,
-SSE and counters) followed by the centre update (deterministic segmented FP64
-reduction, division, FP32 rounding, largest centre move).  Inputs are
+MFMA cross term, reliability test, FP64 correction, argmin and counters)
+followed by the centre update (deterministic segmented FP64 reduction,
+division, FP32 rounding, largest centre move, and the pass's SSE in FP64 from
+the same read of X).  Inputs are
 resident in HBM before timing starts.
 
 Prints ONE JSON line.  Extra keys report the assignment kernel alone, the
@@ -168,9 +169,13 @@ def main():
     prec = km.Precision(km.KM_LOW_FP16, km.KM_ALPHA_PAPER_EQ, 5.0)
     stream = torch.cuda.current_stream()
 
+    sse = torch.empty(1, dtype=torch.float64, device="cuda")
+
     def step(c_in, c_out):
+        # the pass's SSE is taken by the update, which reads every point's
+        # row against the centre it was assigned to
         km.kmeans_assign(ctx, X, c_in, prec, labels=labels, stats=False, stream=stream)
-        km.kmeans_update(ctx, X, labels, c_in, C_new=c_out, shift=shift, stream=stream)
+        km.kmeans_update(ctx, X, labels, c_in, C_new=c_out, shift=shift, sse=sse, stream=stream)
 
     bufs = [Ca, Cb]
     for i in range(args.warmup):

@@ -150,12 +150,17 @@ int32_t kmeans_assign(km_context *ctx, const float *X, int64_t n, int32_t d,
 /* ---- one centre update (eq:center, Algorithm alg:mp-kmeans) -----------------
  * C_new[j] = fl32( (sum_{i: labels_i = j} x_i) / m_j ) with the sums taken in
  * FP64 in a fixed order that does not depend on the launch (points of a
- * cluster in ascending index, in chunks of 256); an empty cluster keeps
+ * cluster in ascending index, in chunks of 64); an empty cluster keeps
  * C_old[j].  counts [k] int64 and shift [1] FP64 (max_j ||C_new-C_old||) are
- * device outputs, nullable.  labels must lie in [0,k). */
+ * device outputs, nullable.  sse [1] FP64 device scalar, nullable: the SSE of
+ * the given labels against C_old (eq:sse), sum_i ||x_i - C_old[label_i]||^2
+ * in FP64 from the FP32 data, accumulated in a fixed order while the update
+ * reads every point's row -- the SSE of the assignment pass that produced
+ * the labels, without that pass refining its winners.  labels must lie in
+ * [0,k). */
 int32_t kmeans_update(km_context *ctx, const float *X, int64_t n, int32_t d,
                       const int32_t *labels, int32_t k, const float *C_old,
-                      float *C_new, int64_t *counts, double *shift,
+                      float *C_new, int64_t *counts, double *shift, double *sse,
                       void *stream, uint32_t flags);
 
 /* ---- Lloyd's algorithm (Algorithm alg:mp-kmeans) ---------------------------

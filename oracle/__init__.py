@@ -76,6 +76,8 @@ def lib():
             L.oracle_dist_rows.argtypes = [P, i64, i32, P, i32, P]
             L.oracle_assign.restype = None
             L.oracle_assign.argtypes = [P, i64, i32, P, i32, P, P, P]
+            L.oracle_sse_labels.restype = dbl
+            L.oracle_sse_labels.argtypes = [P, i64, i32, P, P, i32]
             L.oracle_update.restype = i64
             L.oracle_update.argtypes = [P, i64, i32, P, i32, P, P, P, P]
             L.oracle_lloyd.restype = i32
@@ -172,6 +174,17 @@ def assign(X, C):
     lib().oracle_assign(_ptr(X), n, d, _ptr(C), k, _ptr(labels), _ptr(mind),
                         ct.byref(sse))
     return labels, mind, sse.value
+
+
+def sse_labels(X, C, labels) -> float:
+    """eq:sse of a given assignment: sum_i ||x_i - c_{labels_i}||^2, each
+    term by the FP64 direct formula, pairwise summed (O1's order)."""
+    X, C = _f32(X), _f32(C)
+    labels = np.ascontiguousarray(labels, dtype=np.int32)
+    v = lib().oracle_sse_labels(_ptr(X), X.shape[0], X.shape[1], _ptr(labels), _ptr(C), C.shape[0])
+    if v < 0:
+        raise ValueError("label out of range")
+    return v
 
 
 def update(X, labels, C_old):

@@ -186,6 +186,24 @@ void oracle_assign(const float *X, int64_t n, int d, const float *C, int k,
   if (mind == NULL) free(md);
 }
 
+/* eq:sse for a given assignment: the pairwise sum over i of the FP64 direct
+ * distance d(x_i, c_{labels_i}) (the same terms and order as O1's SSE when
+ * the labels are O1's).  Returns -1 on a label out of range. */
+double oracle_sse_labels(const float *X, int64_t n, int d, const int32_t *labels,
+                         const float *C, int k) {
+  double *t = (double *)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
+  for (int64_t i = 0; i < n; ++i) {
+    if (labels[i] < 0 || labels[i] >= k) {
+      free(t);
+      return -1.0;
+    }
+    t[i] = oracle_sqdist(X + i * (int64_t)d, C + (int64_t)labels[i] * d, d);
+  }
+  double s = pairwise_sum(t, n);
+  free(t);
+  return s;
+}
+
 /* ---------------------------------------------------------------------- */
 /* O2: centre update                                                       */
 /* ---------------------------------------------------------------------- */

@@ -97,7 +97,7 @@ def lib():
                 "kmeans_context_create": [i32, ct.POINTER(P)],
                 "kmeans_context_destroy": [P],
                 "kmeans_assign": [P, P, i64, i32, P, i32, PP, P, P, P, PS, P, u32],
-                "kmeans_update": [P, P, i64, i32, P, i32, P, P, P, P, P, u32],
+                "kmeans_update": [P, P, i64, i32, P, i32, P, P, P, P, P, P, u32],
                 "kmeans_lloyd": [P, P, i64, i32, i32, P, i32, dbl, PP, P, P, P, PS, P, u32],
                 "kmeans_solve_batch": [P, ct.POINTER(Problem), i32, PP, P, u32],
                 "kmeans_pairwise": [P, P, i64, i32, P, i32, PP, P, P, P, u32],
@@ -291,7 +291,10 @@ def kmeans_quantize(ctx: Context, x, low=KM_LOW_FP16, out=None, stream=None,
 
 
 def kmeans_update(ctx: Context, X, labels, C_old, C_new=None, counts=None,
-                  shift=None, stream=None, sync=False):
+                  shift=None, sse=None, stream=None, sync=False):
+    """One centre update.  ``counts``, ``shift`` and ``sse`` are optional
+    device outputs (pass True to allocate).  Returns
+    ``(C_new, counts, shift, sse)``."""
     torch = _torch()
     n, d = X.shape
     k = C_old.shape[0]
@@ -301,6 +304,8 @@ def kmeans_update(ctx: Context, X, labels, C_old, C_new=None, counts=None,
         counts = torch.empty(k, dtype=torch.int64, device=X.device)
     if shift is True:
         shift = torch.empty(1, dtype=torch.float64, device=X.device)
+    if sse is True:
+        sse = torch.empty(1, dtype=torch.float64, device=X.device)
     code = lib().kmeans_update(
         ctx.handle, _dev_ptr(X, torch.float32, "X", n * d), n, d,
         _dev_ptr(labels, torch.int32, "labels", n), k,
@@ -308,9 +313,10 @@ def kmeans_update(ctx: Context, X, labels, C_old, C_new=None, counts=None,
         _dev_ptr(C_new, torch.float32, "C_new", k * d),
         _dev_ptr(counts, torch.int64, "counts", k, allow_none=True),
         _dev_ptr(shift, torch.float64, "shift", 1, allow_none=True),
+        _dev_ptr(sse, torch.float64, "sse", 1, allow_none=True),
         _stream_ptr(stream), KM_SYNC if sync else 0)
     _check(code, "kmeans_update")
-    return C_new, counts, shift
+    return C_new, counts, shift, sse
 
 
 def kmeans_lloyd(ctx: Context, X, C_inout, max_iter: int, tol: float = 0.0,

@@ -138,6 +138,27 @@ AssignPlan plan_assign(const km_precision& p, int64_t n, int d, int k) {
 // ---------------------------------------------------------------------------
 // Launch helpers
 // ---------------------------------------------------------------------------
+// Several host arrays gathered into one upload (one H2D copy per call).
+struct Pack {
+  std::vector<char> buf;
+  size_t add(const void* p, size_t n) {
+    const size_t off = (buf.size() + 255) & ~size_t(255);
+    buf.resize(off + n);
+    memcpy(buf.data() + off, p, n);
+    return off;
+  }
+  char* upload(km_context_impl* ctx, hipStream_t st) {
+    return static_cast<char*>(ctx->up.put(buf.data(), buf.size(), st));
+  }
+};
+
+// One clearing launch for the status word and the result record that follow
+// it in the arena.
+static hipError_t zero_status_result(int* status, KResult* result, hipStream_t st) {
+  const size_t span = (size_t)(reinterpret_cast<char*>(result + 1) - reinterpret_cast<char*>(status));
+  return launch_zero_words(status, span, st);
+}
+
 static std::vector<int32_t> prefix(const std::vector<int>& counts) {
   std::vector<int32_t> s(counts.size() + 1, 0);
   for (size_t i = 0; i < counts.size(); ++i) s[i + 1] = s[i] + counts[i];
@@ -149,10 +170,12 @@ hipError_t run_prep(km_context_impl* ctx, int low, const std::vector<PrepProb>& 
   std::vector<int> wgs(kpads.size());
   for (size_t i = 0; i < kpads.size(); ++i) wgs[i] = (kpads[i] + 3) / 4;  // one wave per centre
   std::vector<int32_t> pre = prefix(wgs);
-  void* dp = ctx->up.put(probs.data(), probs.size() * sizeof(PrepProb), st);
-  void* ds = ctx->up.put(pre.data(), pre.size() * sizeof(int32_t), st);
-  if (!dp || !ds) return hipErrorOutOfMemory;
-  return launch_prep(low, (const PrepProb*)dp, (const int32_t*)ds, (int)probs.size(), pre.back(), st);
+  Pack pk;
+  const size_t op = pk.add(probs.data(), probs.size() * sizeof(PrepProb));
+  const size_t os = pk.add(pre.data(), pre.size() * sizeof(int32_t));
+  char* d = pk.upload(ctx, st);
+  if (!d) return hipErrorOutOfMemory;
+  return launch_prep(low, (const PrepProb*)(d + op), (const int32_t*)(d + os), (int)probs.size(), pre.back(), st);
 }
 
 hipEvent_t km_context_impl::timing_event(int i) {
@@ -164,13 +187,25 @@ hipEvent_t km_context_impl::timing_event(int i) {
   return ev_pool[i];
 }
 
+static hipError_t run_assign_dev(km_context_impl* ctx, const AssignPlan& shape, int mode, const void* dp,
+                                 const void* ds, int nprob, int total_wg, hipStream_t st);
+
 hipError_t run_assign(km_context_impl* ctx, const AssignPlan& shape, int mode,
                       const std::vector<AssignProb>& probs, const std::vector<int>& nwgs, hipStream_t st) {
   std::vector<int32_t> pre = prefix(nwgs);
   if (pre.back() == 0) return hipSuccess;
-  void* dp = ctx->up.put(probs.data(), probs.size() * sizeof(AssignProb), st);
-  void* ds = ctx->up.put(pre.data(), pre.size() * sizeof(int32_t), st);
-  if (!dp || !ds) return hipErrorOutOfMemory;
+  Pack pk;
+  const size_t op = pk.add(probs.data(), probs.size() * sizeof(AssignProb));
+  const size_t os = pk.add(pre.data(), pre.size() * sizeof(int32_t));
+  char* d = pk.upload(ctx, st);
+  if (!d) return hipErrorOutOfMemory;
+  return run_assign_dev(ctx, shape, mode, d + op, d + os, (int)probs.size(), pre.back(), st);
+}
+
+// The assignment launch of problems whose descriptors are already on the
+// device, bracketed by timing events when timing is enabled.
+static hipError_t run_assign_dev(km_context_impl* ctx, const AssignPlan& shape, int mode, const void* dp,
+                                 const void* ds, int nprob, int total_wg, hipStream_t st) {
   hipEvent_t e0 = nullptr, e1 = nullptr;
   if (ctx->timing) {
     e0 = ctx->timing_event(2 * ctx->ev_used);
@@ -184,12 +219,12 @@ hipError_t run_assign(km_context_impl* ctx, const AssignPlan& shape, int mode,
     case Route::Mfma:
     case Route::MfmaNoFallback:
       e = launch_assign_mfma(shape.low, shape.DP, mode, shape.route == Route::Mfma, (const AssignProb*)dp,
-                             (const int32_t*)ds, (int)probs.size(), pre.back(), st);
+                             (const int32_t*)ds, nprob, total_wg, st);
       break;
     case Route::Direct64Exact:
     case Route::Direct64All:
       e = launch_assign_direct64(shape.route == Route::Direct64Exact, mode, (const AssignProb*)dp,
-                                 (const int32_t*)ds, (int)probs.size(), pre.back(), st);
+                                 (const int32_t*)ds, nprob, total_wg, st);
       break;
   }
   if (e == hipSuccess && ctx->timing) {
@@ -213,6 +248,7 @@ void plan_update(Plan& pl, int64_t n, int d, int k) {
   pl.add<int32_t>((size_t)k + 1);       // cstart
   pl.add<int32_t>((size_t)k + 1);       // chunk_start
   pl.add<double>(((size_t)(n + kUpdChunk - 1) / kUpdChunk + k) * d);  // chunk sums
+  pl.add<double>((size_t)(n + kUpdChunk - 1) / kUpdChunk + k);        // chunk SSE partials
   pl.add<double>((size_t)k);            // shift2
 }
 
@@ -225,7 +261,9 @@ UpdateProb carve_update(Arena& a, int64_t n, int d, int k) {
   u.cstart = a.take<int32_t>((size_t)k + 1);
   u.chunk_start = a.take<int32_t>((size_t)k + 1);
   u.chunk_sum = a.take<double>(((size_t)(n + kUpdChunk - 1) / kUpdChunk + k) * d);
+  u.sse_chunk = a.take<double>((size_t)(n + kUpdChunk - 1) / kUpdChunk + k);
   u.shift2 = a.take<double>((size_t)k);
+  u.sse_out = nullptr;
   u.n = n;
   u.d = d;
   u.k = k;
@@ -248,10 +286,12 @@ hipError_t run_update(km_context_impl* ctx, const std::vector<UpdateProb>& probs
     std::vector<int32_t> p = prefix(*v);
     pre.insert(pre.end(), p.begin(), p.end());
   }
-  void* dp = ctx->up.put(probs.data(), probs.size() * sizeof(UpdateProb), st);
-  void* ds = ctx->up.put(pre.data(), pre.size() * sizeof(int32_t), st);
-  if (!dp || !ds) return hipErrorOutOfMemory;
-  return launch_update((const UpdateProb*)dp, probs.data(), np, (const int32_t*)ds, st);
+  Pack pk;
+  const size_t op = pk.add(probs.data(), probs.size() * sizeof(UpdateProb));
+  const size_t os = pk.add(pre.data(), pre.size() * sizeof(int32_t));
+  char* d = pk.upload(ctx, st);
+  if (!d) return hipErrorOutOfMemory;
+  return launch_update((const UpdateProb*)(d + op), probs.data(), np, (const int32_t*)(d + os), st);
 }
 
 }  // namespace km
@@ -398,8 +438,13 @@ bool uses_prep(const AssignPlan& a) { return a.route == Route::Mfma || a.route =
 static hipError_t enqueue_pass(km_context_impl* ctx, const AssignPlan& a, const PassBufs& b,
                                const float* X, int64_t n, int d, const float* C, int k, int32_t* labels,
                                float* mindist, double* sse_slot, int mode, float* D, uint8_t* flagged,
-                               hipStream_t st) {
-  if (uses_prep(a)) {
+                               bool refine, hipStream_t st) {
+  // every descriptor of the pass in one upload
+  Pack pk;
+  const bool prep = uses_prep(a);
+  size_t o_pp = 0, o_ps = 0;
+  int prep_wg = 0;
+  if (prep) {
     PrepProb pp{};
     pp.C = C;
     pp.Cq = b.Cq;
@@ -411,8 +456,10 @@ static hipError_t enqueue_pass(km_context_impl* ctx, const AssignPlan& a, const 
     pp.k_pad = a.k_pad;
     pp.d = d;
     pp.DP = a.DP;
-    hipError_t e = run_prep(ctx, a.low, {pp}, {a.k_pad}, st);
-    if (e != hipSuccess) return e;
+    prep_wg = (a.k_pad + 3) / 4;  // one wave per centre
+    const int32_t pre[2] = {0, prep_wg};
+    o_pp = pk.add(&pp, sizeof(pp));
+    o_ps = pk.add(pre, sizeof(pre));
   }
   AssignProb ap{};
   ap.X = X;
@@ -432,9 +479,11 @@ static hipError_t enqueue_pass(km_context_impl* ctx, const AssignPlan& a, const 
   ap.k = k;
   ap.k_pad = a.k_pad;
   ap.oma = a.oma;
+  ap.refine = refine ? 1 : 0;
   const int nwg = mode == 0 ? a.nwg : a.nwg_pair;
-  hipError_t e = run_assign(ctx, a, mode, {ap}, {nwg}, st);
-  if (e != hipSuccess) return e;
+  const int32_t apre[2] = {0, nwg};
+  const size_t o_ap = pk.add(&ap, sizeof(ap));
+  const size_t o_as = pk.add(apre, sizeof(apre));
   ReduceProb rp{};
   rp.sse_part = b.sse_part;
   rp.corr_part = b.corr_part;
@@ -443,7 +492,17 @@ static hipError_t enqueue_pass(km_context_impl* ctx, const AssignPlan& a, const 
   rp.result = b.result;
   rp.pairs = n * (long long)k;
   rp.nparts = nwg;
-  return run_reduce(ctx, {rp}, st);
+  const size_t o_rp = pk.add(&rp, sizeof(rp));
+  char* dv = pk.upload(ctx, st);
+  if (!dv) return hipErrorOutOfMemory;
+  hipError_t e;
+  if (prep) {
+    e = launch_prep(a.low, (const PrepProb*)(dv + o_pp), (const int32_t*)(dv + o_ps), 1, prep_wg, st);
+    if (e != hipSuccess) return e;
+  }
+  e = run_assign_dev(ctx, a, mode, dv + o_ap, dv + o_as, 1, nwg, st);
+  if (e != hipSuccess) return e;
+  return launch_reduce_parts((const ReduceProb*)(dv + o_rp), 1, st);
 }
 
 static int32_t finish_stats(km_context_impl* ctx, const KResult* dres, km_stats* stats, const AssignPlan& a,
@@ -485,9 +544,10 @@ int32_t kmeans_assign(km_context* ctx, const float* X, int64_t n, int32_t d, con
   KM_HIP(ctx->arena.ensure(pl.bytes));
   ctx->arena.reset();
   PassBufs b = carve_pass(ctx->arena, a);
-  KM_HIP(hipMemsetAsync(b.status, 0, sizeof(int), st));
-  KM_HIP(hipMemsetAsync(b.result, 0, sizeof(KResult), st));
-  KM_HIP(enqueue_pass(ctx, a, b, X, n, d, C, k, labels, mindist, sse, 0, nullptr, nullptr, st));
+  KM_HIP(zero_status_result(b.status, b.result, st));
+  // the FP64 winner refinement only when distances or the SSE are wanted
+  const bool refine = mindist || sse || stats;
+  KM_HIP(enqueue_pass(ctx, a, b, X, n, d, C, k, labels, mindist, sse, 0, nullptr, nullptr, refine, st));
   if (stats || (flags & KM_SYNC)) return finish_stats(ctx, b.result, stats, a, 0, st);
   return KM_OK;
 }
@@ -508,9 +568,8 @@ int32_t kmeans_pairwise(km_context* ctx, const float* X, int64_t m, int32_t d, c
   KM_HIP(ctx->arena.ensure(pl.bytes));
   ctx->arena.reset();
   PassBufs b = carve_pass(ctx->arena, a);
-  KM_HIP(hipMemsetAsync(b.status, 0, sizeof(int), st));
-  KM_HIP(hipMemsetAsync(b.result, 0, sizeof(KResult), st));
-  KM_HIP(enqueue_pass(ctx, a, b, X, m, d, C, k, nullptr, nullptr, nullptr, 1, D, flagged, st));
+  KM_HIP(zero_status_result(b.status, b.result, st));
+  KM_HIP(enqueue_pass(ctx, a, b, X, m, d, C, k, nullptr, nullptr, nullptr, 1, D, flagged, true, st));
   if (flags & KM_SYNC) return finish_stats(ctx, b.result, nullptr, a, 0, st);
   return KM_OK;
 }
@@ -526,8 +585,8 @@ int32_t kmeans_quantize(km_context* ctx, const float* in, int64_t count, int32_t
 }
 
 int32_t kmeans_update(km_context* ctx, const float* X, int64_t n, int32_t d, const int32_t* labels, int32_t k,
-                      const float* C_old, float* C_new, int64_t* counts, double* shift, void* stream,
-                      uint32_t flags) {
+                      const float* C_old, float* C_new, int64_t* counts, double* shift, double* sse,
+                      void* stream, uint32_t flags) {
   if (!ctx || !X || !labels || !C_old || !C_new || C_old == C_new) return KM_ERR_ARG;
   if (n < 1 || n > (int64_t)INT32_MAX - 1024 || d < 1 || k < 1 || k > 65536) return KM_ERR_ARG;
   hipStream_t st = (hipStream_t)stream;
@@ -541,14 +600,14 @@ int32_t kmeans_update(km_context* ctx, const float* X, int64_t n, int32_t d, con
   UpdateProb u = carve_update(ctx->arena, n, d, k);
   int* status = ctx->arena.take<int>(1);
   KResult* res = ctx->arena.take<KResult>(1);
-  KM_HIP(hipMemsetAsync(status, 0, sizeof(int), st));
-  KM_HIP(hipMemsetAsync(res, 0, sizeof(KResult), st));
+  KM_HIP(zero_status_result(status, res, st));
   u.X = X;
   u.labels = labels;
   u.C_old = C_old;
   u.C_new = C_new;
   u.counts_out = reinterpret_cast<long long*>(counts);
   u.shift_out = shift;
+  u.sse_out = sse;
   u.result = res;
   u.status = status;
   KM_HIP(run_update(ctx, {u}, st));
@@ -581,8 +640,7 @@ int32_t kmeans_lloyd(km_context* ctx, const float* X, int64_t n, int32_t d, int3
   PassBufs b = carve_pass(ctx->arena, a);
   UpdateProb u = carve_update(ctx->arena, n, d, k);
   float* Cw = ctx->arena.take<float>((size_t)k * d);
-  KM_HIP(hipMemsetAsync(b.status, 0, sizeof(int), st));
-  KM_HIP(hipMemsetAsync(b.result, 0, sizeof(KResult), st));
+  KM_HIP(zero_status_result(b.status, b.result, st));
   u.X = X;
   u.labels = labels;
   u.result = b.result;
@@ -591,10 +649,12 @@ int32_t kmeans_lloyd(km_context* ctx, const float* X, int64_t n, int32_t d, int3
   float* nxt = Cw;
   int32_t it = 0;
   for (; it < max_iter; ++it) {
-    KM_HIP(enqueue_pass(ctx, a, b, X, n, d, cur, k, labels, nullptr, sse_hist ? sse_hist + it : nullptr, 0,
-                        nullptr, nullptr, st));
+    // the SSE of a round's pass comes from the update, which reads every
+    // point's row against the centre it was assigned to
+    KM_HIP(enqueue_pass(ctx, a, b, X, n, d, cur, k, labels, nullptr, nullptr, 0, nullptr, nullptr, false, st));
     u.C_old = cur;
     u.C_new = nxt;
+    u.sse_out = sse_hist ? sse_hist + it : nullptr;
     KM_HIP(run_update(ctx, {u}, st));
     std::swap(cur, nxt);
     if (tol > 0.0) {
@@ -607,7 +667,7 @@ int32_t kmeans_lloyd(km_context* ctx, const float* X, int64_t n, int32_t d, int3
     }
   }
   KM_HIP(enqueue_pass(ctx, a, b, X, n, d, cur, k, labels, mindist, sse_hist ? sse_hist + it : nullptr, 0,
-                      nullptr, nullptr, st));
+                      nullptr, nullptr, true, st));
   if (cur != C_inout)
     KM_HIP(hipMemcpyAsync(C_inout, cur, sizeof(float) * (size_t)k * d, hipMemcpyDeviceToDevice, st));
   if (stats || (flags & KM_SYNC)) return finish_stats(ctx, b.result, stats, a, it, st);
@@ -681,6 +741,7 @@ hipError_t enqueue_batch_pass(km_context_impl* ctx, std::vector<BatchState*>& li
       a.k = s->prob->k;
       a.k_pad = o.k_pad;
       a.oma = o.oma;
+      a.refine = final_pass ? 1 : 0;
       ap.push_back(a);
       nw.push_back(o.nwg);
     }
@@ -694,7 +755,7 @@ hipError_t enqueue_batch_pass(km_context_impl* ctx, std::vector<BatchState*>& li
     r.sse_part = s->bufs.sse_part;
     r.corr_part = s->bufs.corr_part;
     r.status = s->bufs.status;
-    r.sse_out = s->prob->sse_hist ? s->prob->sse_hist + s->it : nullptr;
+    r.sse_out = (final_pass && s->prob->sse_hist) ? s->prob->sse_hist + s->it : nullptr;
     r.result = s->bufs.result;
     r.pairs = s->prob->n * (long long)s->prob->k;
     r.nparts = s->plan.nwg;
@@ -711,6 +772,7 @@ hipError_t enqueue_batch_round(km_context_impl* ctx, std::vector<BatchState*>& a
   for (BatchState* s : act) {
     s->upd.C_old = s->cur;
     s->upd.C_new = s->nxt;
+    s->upd.sse_out = s->prob->sse_hist ? s->prob->sse_hist + s->it : nullptr;
     up.push_back(s->upd);
   }
   e = run_update(ctx, up, st);
@@ -763,8 +825,7 @@ extern "C" int32_t kmeans_solve_batch(km_context* ctx, km_problem* probs, int32_
     s.upd.labels = s.prob->labels;
     s.upd.result = s.bufs.result;
     s.upd.status = s.bufs.status;
-    KM_HIP(hipMemsetAsync(s.bufs.status, 0, sizeof(int), st));
-    KM_HIP(hipMemsetAsync(s.bufs.result, 0, sizeof(KResult), st));
+    KM_HIP(zero_status_result(s.bufs.status, s.bufs.result, st));
     s.done = s.prob->max_iter == 0;
   }
   (void)results;

@@ -918,7 +918,7 @@ k_assign_pipe(const AssignProb* __restrict__ probs, const int32_t* __restrict__ 
   {
     int nloc = nvalid - pw;
     nloc = nloc < 0 ? 0 : (nloc > NB * 32 ? NB * 32 : nloc);
-    sse = refine_wave(P, p0 + pw, nloc, s_lab[wave], lane);
+    if (P.refine) sse = refine_wave(P, p0 + pw, nloc, s_lab[wave], lane);
   }
   sse = wave_sum(sse);
   unsigned long long nc = wave_sum_u64(ncorr);
@@ -1057,10 +1057,12 @@ k_assign_direct64(const AssignProb* __restrict__ probs, const int32_t* __restric
       }
       const int64_t p = p0 + tid;
       if (bi < 0) bi = 0;  // only with non-finite data (status raised)
-      const double dd = sqdist64(P.X + p * d, P.C + (int64_t)bi * d, d);
       as_global(P.labels)[p] = bi;
-      if (P.mindist) as_global(P.mindist)[p] = (float)dd;
-      sse = dd;
+      if (P.refine) {
+        const double dd = sqdist64(P.X + p * d, P.C + (int64_t)bi * d, d);
+        if (P.mindist) as_global(P.mindist)[p] = (float)dd;
+        sse = dd;
+      }
     }
   }
   if (!CMP64 && tid < TP && tid < nvalid) nc = (unsigned long long)k;
@@ -1201,6 +1203,18 @@ hipError_t launch_assign_direct64(bool cmp64, int mode, const AssignProb* dprobs
   } else {
     hipLaunchKernelGGL((k_assign_direct64<true, 1>), dim3(nwg), dim3(256), 0, st, dprobs, dstart, nprob);
   }
+  return hipGetLastError();
+}
+
+// Clears a small device range (status words and result records before a
+// pass): one launch, and usable where a memset node is not.
+__global__ void __launch_bounds__(256) k_zero_words(uint32_t* __restrict__ p, int nwords) {
+  for (int i = threadIdx.x; i < nwords; i += 256) as_global(p)[i] = 0u;
+}
+
+hipError_t launch_zero_words(void* p, size_t bytes, hipStream_t st) {
+  const int nwords = (int)((bytes + 3) / 4);
+  hipLaunchKernelGGL(k_zero_words, dim3(1), dim3(256), 0, st, reinterpret_cast<uint32_t*>(p), nwords);
   return hipGetLastError();
 }
 

@@ -74,6 +74,8 @@ struct AssignProb {
   int64_t n;
   int d, k, k_pad;
   float oma;            // 1 - alpha (FP32)
+  int refine;           // 1: FP64 winner refinement, mindist and SSE partials;
+                        // 0: labels and counters only (SSE left to the update)
 };
 
 struct ReduceProb {
@@ -101,8 +103,10 @@ struct UpdateProb {
   int32_t* perm;           // n
   int32_t* cstart;         // k+1 cluster starts in perm
   int32_t* chunk_start;    // k+1 chunk starts
-  double* chunk_sum;       // (n/256 + k) * d
+  double* chunk_sum;       // (n/64 + k) * d
+  double* sse_chunk;       // n/64 + k: per-chunk SSE partials
   double* shift2;          // k
+  double* sse_out;         // nullable: SSE of the labels against C_old (FP64)
   int* status;
   int64_t n;
   int d, k, ntiles;
@@ -115,6 +119,7 @@ hipError_t launch_assign_mfma(int low, int DP, int mode, bool fallback, const As
 hipError_t launch_assign_direct64(bool cmp64, int mode, const AssignProb* dprobs, const int32_t* dstart,
                                   int nprob, int nwg, hipStream_t st);
 hipError_t launch_reduce_parts(const ReduceProb* dprobs, int nprob, hipStream_t st);
+hipError_t launch_zero_words(void* p, size_t bytes, hipStream_t st);  // bytes rounded up to 4
 hipError_t launch_quantize(int low, const float* in, int64_t count, uint16_t* out, hipStream_t st);
 
 // centre update (km_update.hip)

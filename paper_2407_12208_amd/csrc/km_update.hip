@@ -18,7 +18,10 @@
 //   6. finalize  per cluster, sum of its chunk partials in order, division,
 //                one rounding to FP32, empty clusters keep their centre,
 //                squared move;
-//   7. shift     per problem, max_j ||c_j^new - c_j^old|| (FP64).
+//   7. shift     per problem, max_j ||c_j^new - c_j^old|| (FP64), and, when
+//                asked, the SSE of the labels against C_old: per-chunk FP64
+//                partials from the chunk sums (they read every member row
+//                anyway), summed per cluster by finalize, then over clusters.
 // No floating-point atomics anywhere.
 #include "km_device.hpp"
 #include "km_internal.hpp"
@@ -207,7 +210,7 @@ k_upd_scatter(const UpdateProb* __restrict__ probs, const int32_t* __restrict__ 
 // coordinate per lane (L = lanes for d, up to 64, several coordinates per
 // lane beyond 64).
 template <bool VEC>
-__device__ inline void chunk_rows(const UpdateProb& P, int c, int m0, int m1, int lane) {
+__device__ inline void chunk_rows(const UpdateProb& P, int c, int j, int m0, int m1, int lane) {
   const int d = P.d;
   const int per = VEC ? 4 : 1;              // coordinates per load
   const int nv = (d + per - 1) / per;       // loads per row
@@ -223,6 +226,22 @@ __device__ inline void chunk_rows(const UpdateProb& P, int c, int m0, int m1, in
 #pragma unroll
     for (int e = 0; e < 4; ++e) s[q][e] = 0.0;
   const KM_GLOBAL float* __restrict__ X = as_global(P.X);
+  // SSE against the centre the members were assigned to: this lane's
+  // coordinates of C_old[j] (zero where the lane holds none)
+  const bool want_sse = P.sse_out != nullptr;
+  double e2 = 0.0;
+  double cv[kMaxSlots][4];
+#pragma unroll
+  for (int q = 0; q < kMaxSlots; ++q)
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int l = per * (cl + 64 * q) + e;
+      cv[q][e] = (want_sse && q < nslot && e < per && l < d) ? (double)as_global(P.C_old)[(int64_t)j * d + l] : 0.0;
+    }
+  auto add_sq = [&](int q, int e, float x) {
+    const double t = (double)x - cv[q][e];
+    e2 = __builtin_fma(t, t, e2);
+  };
   auto add_row = [&](int id) {
 #pragma unroll
     for (int q = 0; q < kMaxSlots; ++q) {
@@ -235,8 +254,16 @@ __device__ inline void chunk_rows(const UpdateProb& P, int c, int m0, int m1, in
         s[q][1] += (double)x.y;
         s[q][2] += (double)x.z;
         s[q][3] += (double)x.w;
+        if (want_sse) {
+          add_sq(q, 0, x.x);
+          add_sq(q, 1, x.y);
+          add_sq(q, 2, x.z);
+          add_sq(q, 3, x.w);
+        }
       } else {
-        s[q][0] += (double)X[(int64_t)id * d + v];
+        const float x = X[(int64_t)id * d + v];
+        s[q][0] += (double)x;
+        if (want_sse) add_sq(q, 0, x);
       }
     }
   };
@@ -259,6 +286,15 @@ __device__ inline void chunk_rows(const UpdateProb& P, int c, int m0, int m1, in
         s[0][1] += (double)xv[u].y;
         s[0][2] += (double)xv[u].z;
         s[0][3] += (double)xv[u].w;
+      }
+      if (want_sse && on) {
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          add_sq(0, 0, xv[u].x);
+          add_sq(0, 1, xv[u].y);
+          add_sq(0, 2, xv[u].z);
+          add_sq(0, 3, xv[u].w);
+        }
       }
     } else {
 #pragma unroll
@@ -286,6 +322,10 @@ __device__ inline void chunk_rows(const UpdateProb& P, int c, int m0, int m1, in
       }
     }
   }
+  if (want_sse) {
+    e2 = wave_sum(e2);
+    if (lane == 0) as_global(P.sse_chunk)[c] = e2;
+  }
 }
 
 __global__ void __launch_bounds__(256)
@@ -305,9 +345,9 @@ k_upd_chunksum(const UpdateProb* __restrict__ probs, const int32_t* __restrict__
   const int m0 = as_global(P.cstart)[j] + (c - as_global(P.chunk_start)[j]) * kUpdChunk;
   const int m1 = (m0 + kUpdChunk) < as_global(P.cstart)[j + 1] ? (m0 + kUpdChunk) : as_global(P.cstart)[j + 1];
   if ((P.d & 3) == 0 && (((uintptr_t)P.X) & 15) == 0)
-    chunk_rows<true>(P, c, m0, m1, lane);
+    chunk_rows<true>(P, c, j, m0, m1, lane);
   else
-    chunk_rows<false>(P, c, m0, m1, lane);
+    chunk_rows<false>(P, c, j, m0, m1, lane);
 }
 
 // 6. per cluster: ordered sum of chunk partials, divide, round, keep empty
@@ -338,6 +378,11 @@ k_upd_finalize(const UpdateProb* __restrict__ probs, const int32_t* __restrict__
     }
   }
   mv2 = wave_sum(mv2);
+  if (P.sse_out && lane == 0 && c1 > c0) {  // the cluster's SSE, its chunks in order
+    double e = 0.0;
+    for (int c = c0; c < c1; ++c) e += as_global(P.sse_chunk)[c];
+    as_global(P.sse_chunk)[c0] = e;
+  }
   if (lane == 0) {
     as_global(P.shift2)[j] = mv2;
     if (P.counts_out) as_global(P.counts_out)[j] = mj;
@@ -349,6 +394,22 @@ __global__ void __launch_bounds__(256)
 k_upd_shift(const UpdateProb* __restrict__ probs) {
   __shared__ double mx[256];
   const UpdateProb& P = probs[blockIdx.x];
+  if (P.sse_out) {  // SSE: per-cluster sums (in each cluster's first chunk
+                    // slot), per-thread strided sums, then a fixed tree
+    double e = 0.0;
+    for (int j = threadIdx.x; j < P.k; j += 256) {
+      const int c0 = as_global(P.chunk_start)[j];
+      if (as_global(P.chunk_start)[j + 1] > c0) e += as_global(P.sse_chunk)[c0];
+    }
+    mx[threadIdx.x] = e;
+    __syncthreads();
+    for (int o = 128; o >= 1; o >>= 1) {
+      if (threadIdx.x < o) mx[threadIdx.x] += mx[threadIdx.x + o];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) *as_global(P.sse_out) = mx[0];
+    __syncthreads();
+  }
   double v = 0.0;
   for (int j = threadIdx.x; j < P.k; j += 256) v = __builtin_fmax(v, as_global(P.shift2)[j]);
   mx[threadIdx.x] = v;

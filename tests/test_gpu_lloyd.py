@@ -55,12 +55,15 @@ def test_update_matches_oracle(ctx, n, d, k):
     if k > 3:
         labels[labels == 2] = 3  # cluster 2 empty
     C_old = g.standard_normal((k, d)).astype(np.float32)
-    C_new, counts, shift = km.kmeans_update(ctx, dev(X), dev(labels), dev(C_old),
-                                            counts=True, shift=True, sync=True)
+    C_new, counts, shift, sse = km.kmeans_update(ctx, dev(X), dev(labels), dev(C_old),
+                                                 counts=True, shift=True, sse=True, sync=True)
     ref, rcounts, rshift, empty = oracle.update(X, labels, C_old)
     np.testing.assert_array_equal(host(counts), rcounts)
     assert_within_ulps(host(C_new), ref, 1)
     assert float(host(shift)[0]) == pytest.approx(rshift, rel=1e-6)
+    # SSE of the given labels against C_old (FP64 terms, another summation
+    # order than the oracle's: relative difference of order n * 2^-53)
+    assert float(host(sse)[0]) == pytest.approx(oracle.sse_labels(X, C_old, labels), rel=1e-12)
     if k > 3:
         np.testing.assert_array_equal(host(C_new)[2], C_old[2])
 
@@ -70,8 +73,8 @@ def test_update_is_deterministic(ctx):
     g = np.random.default_rng(1)
     labels = g.integers(0, 50, size=len(X)).astype(np.int32)
     C0 = np.zeros((50, 24), dtype=np.float32)
-    a, _, _ = km.kmeans_update(ctx, dev(X), dev(labels), dev(C0), sync=True)
-    b, _, _ = km.kmeans_update(ctx, dev(X), dev(labels), dev(C0), sync=True)
+    a, _, _, _ = km.kmeans_update(ctx, dev(X), dev(labels), dev(C0), sync=True)
+    b, _, _, _ = km.kmeans_update(ctx, dev(X), dev(labels), dev(C0), sync=True)
     np.testing.assert_array_equal(host(a), host(b))
 
 
@@ -108,7 +111,7 @@ def test_lloyd_step_locked(ctx):
         lab = host(labels)
         check_assignment(X, C, 0, st["alpha_used"], lab, host(mind), float(host(sse)[0]),
                          st["n_corrected"], min_coverage=0.99)
-        C_new, _, _ = km.kmeans_update(ctx, Xd, labels, dev(C), sync=True)
+        C_new, _, _, _ = km.kmeans_update(ctx, Xd, labels, dev(C), sync=True)
         ref, _, _, _ = oracle.update(X, lab, C)
         assert_within_ulps(host(C_new), ref, 1)
         C = host(C_new)
@@ -219,7 +222,7 @@ def test_lloyd_large_blobs_sampled(ctx, prec, fmt):
         lab = host(labels)
         check_assignment(X, C, fmt, st["alpha_used"], lab, host(mind), None, None,
                          min_coverage=0.99, rows=rows)
-        C_new, _, _ = km.kmeans_update(ctx, Xd, labels, dev(C), sync=True)
+        C_new, _, _, _ = km.kmeans_update(ctx, Xd, labels, dev(C), sync=True)
         ref, _, _, _ = oracle.update(X, lab, C)
         assert_within_ulps(host(C_new), ref, 1)
         C = host(C_new)

@@ -160,6 +160,25 @@ def test_pairwise_sum_exact_on_integers():
     assert oracle.pairwise_sum(v) == 10000 * 10001 / 2
 
 
+def test_sse_labels_exact_on_dyadic_data_and_matches_argmin_sse():
+    # eq:sse for given labels: with dyadic coordinates every squared
+    # difference and every sum is exact in FP64, so the oracle must equal the
+    # exact rational sum computed term by term here
+    g = np.random.default_rng(21)
+    n, d, k = 30, 3, 4
+    X = (g.integers(-40, 41, size=(n, d)) / 8.0).astype(np.float32)
+    C = (g.integers(-40, 41, size=(k, d)) / 8.0).astype(np.float32)
+    labels = g.integers(0, k, size=n).astype(np.int32)
+    want = sum(sum((Fraction(float(X[i, l])) - Fraction(float(C[labels[i], l]))) ** 2
+                   for l in range(d)) for i in range(n))
+    assert oracle.sse_labels(X, C, labels) == float(want)
+    # with the nearest-centre labels it is the SSE of O1
+    lab, _, sse = oracle.assign(X, C)
+    assert oracle.sse_labels(X, C, lab) == sse
+    with pytest.raises(ValueError):
+        oracle.sse_labels(X, C, np.full(n, k, np.int32))
+
+
 # ---------------------------------------------------------------------------
 # O2: centre update
 # ---------------------------------------------------------------------------
