@@ -574,10 +574,14 @@ k_assign_pipe(const AssignProb* __restrict__ probs, const int32_t* __restrict__ 
   constexpr int CT = Cfg::kCt;
   constexpr int kQueue = 8;
 
-  __shared__ __attribute__((aligned(16))) unsigned char smem[Cfg::kBytes];
+  // centre tiles, then the saved best blocks [wave][cb][r/4][lane]; before
+  // the sweep the same bytes stage the point rows of the prologue
+  constexpr int kSvBytes = kPipeWaves * NB * 4 * 64 * 16;
+  __shared__ __attribute__((aligned(16))) unsigned char lds_main[Cfg::kBytes + kSvBytes];
+  unsigned char* const smem = lds_main;
+  f32x4 (*const s_sv)[NB][4][64] = reinterpret_cast<f32x4 (*)[NB][4][64]>(lds_main + Cfg::kBytes);
   __shared__ float s_cinit[2][CT];
   __shared__ float s_ca[3][CT];
-  __shared__ f32x4 s_sv[kPipeWaves][NB][4][64];  // saved best block: [wave][cb][r/4][lane]
   __shared__ int s_q[FALLBACK ? kQueue * NT : 1];
   __shared__ int s_lab[kPipeWaves][NB * 32];
   __shared__ double s_sse[Cfg::kWaves];
@@ -601,12 +605,64 @@ k_assign_pipe(const AssignProb* __restrict__ probs, const int32_t* __restrict__ 
   int bad = 0;
   const bool vec4 = ((d & 3) == 0) && ((((uintptr_t)P.X) & 15) == 0);
   const bool fast = vec4 && d == DP && nvalid == Cfg::kPts;
+  // 16-bit formats with full rows: each wave reads its 32-point slices of X
+  // with contiguous 1 KB loads (64 lanes x 16 B), rounds them and stages them
+  // in LDS (rows padded like the centre tiles), then reads its fragments
+  // back; strided 16-byte fragment loads straight from HBM would touch 32
+  // cache lines per instruction.
+  constexpr bool kStageable = L::KS == 16 && DP <= 128;
+  const bool staged = kStageable && vec4 && d == DP;
+  S* const stg = reinterpret_cast<S*>(lds_main) + wave * 32 * LD;
 #pragma unroll
   for (int cb = 0; cb < NB; ++cb) {
     const int pl = pw + cb * 32 + (lane & 31);
     const bool pv = pl < nvalid;
     const KM_GLOBAL float* xr = as_global(P.X) + (p0 + (pv ? pl : 0)) * d;
     float part = 0.0f;
+    if constexpr (kStageable) {
+      if (staged) {
+        constexpr int kLoads = 32 * DP / 256;  // float4 per lane and load
+        f32x4 xv[kLoads];
+#pragma unroll
+        for (int q = 0; q < kLoads; ++q) {
+          const int f = q * 256 + lane * 4;
+          const int row = f / DP, col = f % DP;
+          const int pr = pw + cb * 32 + row;
+          xv[q] = f32x4{0.f, 0.f, 0.f, 0.f};
+          if (pr < nvalid) xv[q] = *reinterpret_cast<const KM_GLOBAL f32x4*>(as_global(P.X) + (p0 + pr) * d + col);
+        }
+#pragma unroll
+        for (int q = 0; q < kLoads; ++q) {
+          const int f = q * 256 + lane * 4;
+          const int row = f / DP, col = f % DP;
+          typedef S s4 __attribute__((ext_vector_type(4)));
+          s4 h;
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            const float v = xv[q][u];
+            if (!__builtin_isfinite(v)) bad |= kStatusNonFinite;
+            if (L::kHasRange && __builtin_fabsf(v) >= L::kOverflow) bad |= kStatusRange;
+            h[u] = L::cvt(v);
+          }
+          *reinterpret_cast<s4*>(stg + row * LD + col) = h;
+        }
+#pragma unroll
+        for (int s = 0; s < Cfg::kSteps; ++s) {
+          const typename L::frag f =
+              *reinterpret_cast<const typename L::frag*>(stg + (lane & 31) * LD + s * L::KS + (lane >> 5) * L::KV);
+#pragma unroll
+          for (int u = 0; u < L::KV; ++u) {
+            const float qf = L::tof(f[u]);
+            part = __builtin_fmaf(qf, qf, part);
+          }
+          bfr[cb][s] = f;
+        }
+        const float other = __shfl_xor(part, 32, kWave);
+        nx[cb] = (lane < 32) ? part + other : other + part;
+        hx[cb] = pv ? 0.5f * (P.oma * nx[cb]) : __builtin_inff();
+        continue;
+      }
+    }
 #pragma unroll
     for (int s = 0; s < Cfg::kSteps; ++s) {
       const int o = s * L::KS + (lane >> 5) * L::KV;
@@ -814,6 +870,7 @@ k_assign_pipe(const AssignProb* __restrict__ probs, const int32_t* __restrict__ 
   };
 
   load_tile(0);
+  __syncthreads();  // the staged point rows share these LDS bytes
   store_tile(0);
   __syncthreads();
 
