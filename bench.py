@@ -163,7 +163,7 @@ def main():
     X = torch.from_numpy(Xh).cuda()
     Ca = torch.from_numpy(Ch).cuda()
     Cb = torch.empty_like(Ca)
-    labels = torch.empty(n, dtype=torch.int32, device="cuda")
+    labels = torch.zeros(n, dtype=torch.int32, device="cuda")
     shift = torch.empty(1, dtype=torch.float64, device="cuda")
     ctx = km.Context(0)
     prec = km.Precision(km.KM_LOW_FP16, km.KM_ALPHA_PAPER_EQ, 5.0)
@@ -174,7 +174,10 @@ def main():
     def step(c_in, c_out):
         # the pass's SSE is taken by the update, which reads every point's
         # row against the centre it was assigned to
-        km.kmeans_assign(ctx, X, c_in, prec, labels=labels, stats=False, stream=stream)
+        # labels still holds the previous round's assignment: it seeds the
+        # search (Lloyd rounds do the same; results are unchanged)
+        km.kmeans_assign(ctx, X, c_in, prec, labels=labels, stats=False, stream=stream,
+                         labels_hint=True)
         km.kmeans_update(ctx, X, labels, c_in, C_new=c_out, shift=shift, sse=sse, stream=stream)
 
     bufs = [Ca, Cb]

@@ -100,7 +100,10 @@ typedef struct km_stats {
 } km_stats;
 
 /* Flags */
-#define KM_SYNC 1u /* wait for the stream before returning */
+#define KM_SYNC 1u        /* wait for the stream before returning */
+#define KM_LABELS_HINT 2u /* kmeans_assign: labels holds an earlier assignment
+                             (e.g. the previous Lloyd round); it only seeds
+                             the search, the results are the same */
 
 typedef struct km_context km_context;
 typedef struct km_server km_server;
@@ -141,6 +144,11 @@ int32_t kmeans_context_destroy(km_context *ctx);
  *           the direct formula from the FP32 data and rounded once to FP32
  *   sse     [1] FP64 device scalar, nullable: sum of those FP64 distances
  *   stats   host, nullable (forces a wait): counts, alpha, data status
+ * With KM_LABELS_HINT in flags, labels is also read: entries in [0,k) seed
+ * each point's running best (others are ignored); the outputs are identical
+ * to a call without the flag, the sweep only skips saving blocks that cannot
+ * hold the winner.  kmeans_lloyd and the batched solves seed every round
+ * after the first from the previous round's labels.
  * Limits: 1 <= d <= 256, 1 <= k <= 65536, 1 <= n.  k > n is allowed. */
 int32_t kmeans_assign(km_context *ctx, const float *X, int64_t n, int32_t d,
                       const float *C, int32_t k, const km_precision *prec,

@@ -28,6 +28,7 @@ __all__ = [
 KM_LOW_FP16, KM_LOW_BF16, KM_LOW_FP32, KM_EXACT64 = 0, 1, 2, 3
 KM_ALPHA_PAPER_EQ, KM_ALPHA_PAPER_ALG, KM_ALPHA_EXPLICIT, KM_ALPHA_NONE = 0, 1, 2, 3
 KM_SYNC = 1
+KM_LABELS_HINT = 2
 KM_OK, KM_PENDING = 0, 1
 _STATUS_NAMES = {
     0: "KM_OK", 1: "KM_PENDING", -1: "KM_ERR_ARG", -2: "KM_ERR_RANGE",
@@ -230,10 +231,12 @@ def kmeans_alpha(prec=None, d: int = 128) -> float:
 
 
 def kmeans_assign(ctx: Context, X, C, prec=None, labels=None, mindist=None,
-                  sse=None, stats=True, stream=None, sync=False):
+                  sse=None, stats=True, stream=None, sync=False, labels_hint=False):
     """One assignment pass.  X (n,d) and C (k,d) are float32 device tensors.
     Returns ``(labels, mindist, sse, stats_dict_or_None)``; outputs not given
-    are allocated (mindist and sse only when requested with ``True``)."""
+    are allocated (mindist and sse only when requested with ``True``).
+    ``labels_hint=True``: ``labels`` holds an earlier assignment that seeds
+    the search (same results, KM_LABELS_HINT)."""
     torch = _torch()
     n, d = X.shape
     k = C.shape[0]
@@ -251,7 +254,7 @@ def kmeans_assign(ctx: Context, X, C, prec=None, labels=None, mindist=None,
         _dev_ptr(mindist, torch.float32, "mindist", n, allow_none=True),
         _dev_ptr(sse, torch.float64, "sse", 1, allow_none=True),
         ct.byref(st) if st is not None else None, _stream_ptr(stream),
-        KM_SYNC if sync else 0)
+        (KM_SYNC if sync else 0) | (KM_LABELS_HINT if labels_hint else 0))
     _check(code, "kmeans_assign")
     return labels, mindist, sse, (st.as_dict() if st is not None else None)
 

@@ -438,7 +438,7 @@ bool uses_prep(const AssignPlan& a) { return a.route == Route::Mfma || a.route =
 static hipError_t enqueue_pass(km_context_impl* ctx, const AssignPlan& a, const PassBufs& b,
                                const float* X, int64_t n, int d, const float* C, int k, int32_t* labels,
                                float* mindist, double* sse_slot, int mode, float* D, uint8_t* flagged,
-                               bool refine, hipStream_t st) {
+                               bool refine, bool hint, hipStream_t st) {
   // every descriptor of the pass in one upload
   Pack pk;
   const bool prep = uses_prep(a);
@@ -480,6 +480,7 @@ static hipError_t enqueue_pass(km_context_impl* ctx, const AssignPlan& a, const 
   ap.k_pad = a.k_pad;
   ap.oma = a.oma;
   ap.refine = refine ? 1 : 0;
+  ap.hint = hint ? labels : nullptr;
   const int nwg = mode == 0 ? a.nwg : a.nwg_pair;
   const int32_t apre[2] = {0, nwg};
   const size_t o_ap = pk.add(&ap, sizeof(ap));
@@ -547,7 +548,8 @@ int32_t kmeans_assign(km_context* ctx, const float* X, int64_t n, int32_t d, con
   KM_HIP(zero_status_result(b.status, b.result, st));
   // the FP64 winner refinement only when distances or the SSE are wanted
   const bool refine = mindist || sse || stats;
-  KM_HIP(enqueue_pass(ctx, a, b, X, n, d, C, k, labels, mindist, sse, 0, nullptr, nullptr, refine, st));
+  KM_HIP(enqueue_pass(ctx, a, b, X, n, d, C, k, labels, mindist, sse, 0, nullptr, nullptr, refine,
+                      (flags & KM_LABELS_HINT) != 0, st));
   if (stats || (flags & KM_SYNC)) return finish_stats(ctx, b.result, stats, a, 0, st);
   return KM_OK;
 }
@@ -569,7 +571,7 @@ int32_t kmeans_pairwise(km_context* ctx, const float* X, int64_t m, int32_t d, c
   ctx->arena.reset();
   PassBufs b = carve_pass(ctx->arena, a);
   KM_HIP(zero_status_result(b.status, b.result, st));
-  KM_HIP(enqueue_pass(ctx, a, b, X, m, d, C, k, nullptr, nullptr, nullptr, 1, D, flagged, true, st));
+  KM_HIP(enqueue_pass(ctx, a, b, X, m, d, C, k, nullptr, nullptr, nullptr, 1, D, flagged, true, false, st));
   if (flags & KM_SYNC) return finish_stats(ctx, b.result, nullptr, a, 0, st);
   return KM_OK;
 }
@@ -651,7 +653,8 @@ int32_t kmeans_lloyd(km_context* ctx, const float* X, int64_t n, int32_t d, int3
   for (; it < max_iter; ++it) {
     // the SSE of a round's pass comes from the update, which reads every
     // point's row against the centre it was assigned to
-    KM_HIP(enqueue_pass(ctx, a, b, X, n, d, cur, k, labels, nullptr, nullptr, 0, nullptr, nullptr, false, st));
+    KM_HIP(enqueue_pass(ctx, a, b, X, n, d, cur, k, labels, nullptr, nullptr, 0, nullptr, nullptr, false,
+                        it > 0, st));
     u.C_old = cur;
     u.C_new = nxt;
     u.sse_out = sse_hist ? sse_hist + it : nullptr;
@@ -667,7 +670,7 @@ int32_t kmeans_lloyd(km_context* ctx, const float* X, int64_t n, int32_t d, int3
     }
   }
   KM_HIP(enqueue_pass(ctx, a, b, X, n, d, cur, k, labels, mindist, sse_hist ? sse_hist + it : nullptr, 0,
-                      nullptr, nullptr, true, st));
+                      nullptr, nullptr, true, it > 0, st));
   if (cur != C_inout)
     KM_HIP(hipMemcpyAsync(C_inout, cur, sizeof(float) * (size_t)k * d, hipMemcpyDeviceToDevice, st));
   if (stats || (flags & KM_SYNC)) return finish_stats(ctx, b.result, stats, a, it, st);
@@ -742,6 +745,7 @@ hipError_t enqueue_batch_pass(km_context_impl* ctx, std::vector<BatchState*>& li
       a.k_pad = o.k_pad;
       a.oma = o.oma;
       a.refine = final_pass ? 1 : 0;
+      a.hint = s->it > 0 ? s->prob->labels : nullptr;  // the previous round's labels
       ap.push_back(a);
       nw.push_back(o.nwg);
     }

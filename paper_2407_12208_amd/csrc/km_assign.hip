@@ -712,6 +712,58 @@ k_assign_pipe(const AssignProb* __restrict__ probs, const int32_t* __restrict__ 
     cd[cb] = __builtin_inff();
     cj[cb] = -1;
   }
+  // Seed of the running best from an earlier assignment (Lloyd rounds):
+  // W of the hinted pair is recomputed on the vector ALU from the same
+  // rounded operands, and the running best starts just below it, by more
+  // than any difference between two FP32 evaluations of that dot product
+  // (2 gamma_{d+1} at twice the unit roundoff, times the absolute sum).  The
+  // block that holds the maximum still beats the seed, so the result is the
+  // same as without the seed; only the copies of blocks that cannot win are
+  // skipped.  A hinted pair that the reliability test might flag is not used.
+  if (P.hint) {
+    constexpr float kU2 = 1.0f / 8388608.0f;  // 2 * 2^-24
+#pragma unroll
+    for (int cb = 0; cb < NB; ++cb) {
+      const int pl = pw + cb * 32 + (lane & 31);
+      const bool pv = pl < nvalid;
+      const int h = pv ? as_global(P.hint)[p0 + pl] : -1;
+      const bool hv = h >= 0 && h < P.k;
+      // the hinted centre's quantised row, read in the lane's fragment layout
+      const KM_GLOBAL S* cr = reinterpret_cast<const KM_GLOBAL S*>(as_global(P.Cq)) +
+                              (int64_t)(hv ? h : 0) * DP + (lane >> 5) * L::KV;
+      float dp = 0.0f, ap = 0.0f;
+#pragma unroll
+      for (int s = 0; s < Cfg::kSteps; ++s) {
+        typename L::frag cf;
+        if constexpr (L::KV == 1) cf = cr[s * L::KS];
+        else cf = *reinterpret_cast<const KM_GLOBAL typename L::frag*>(cr + s * L::KS);
+#pragma unroll
+        for (int u = 0; u < L::KV; ++u) {
+          float xq, cq;
+          if constexpr (L::KV == 1) {
+            xq = L::tof(bfr[cb][s]);
+            cq = L::tof(cf);
+          } else {
+            xq = L::tof(bfr[cb][s][u]);
+            cq = L::tof(cf[u]);
+          }
+          dp = __builtin_fmaf(xq, cq, dp);
+          ap = __builtin_fmaf(__builtin_fabsf(xq), __builtin_fabsf(cq), ap);
+        }
+      }
+      const float od = __shfl_xor(dp, 32, kWave), oa = __shfl_xor(ap, 32, kWave);
+      const float dot = (lane < 32) ? dp + od : od + dp;
+      const float abs_sum = (lane < 32) ? ap + oa : oa + ap;
+      if (hv && pv) {
+        const float ci = as_global(P.cinit)[h];
+        const float caj = as_global(P.ca)[h];
+        const float m = (float)(d + 1) * kU2;
+        const float delta = 2.0f * (m / (1.0f - m)) * (abs_sum + __builtin_fabsf(ci)) * 1.0625f + 1e-30f;
+        const float w = dot + ci;
+        if ((w + delta) + caj + delta < hx[cb]) bw[cb] = w - 2.0f * delta;
+      }
+    }
+  }
   unsigned long long ncorr = 0;
   int qn = 0;
   auto flush_queue = [&]() {

@@ -76,6 +76,7 @@ struct AssignProb {
   float oma;            // 1 - alpha (FP32)
   int refine;           // 1: FP64 winner refinement, mindist and SSE partials;
                         // 0: labels and counters only (SSE left to the update)
+  const int32_t* hint;  // nullable: an earlier assignment (seeds the search)
 };
 
 struct ReduceProb {

@@ -261,3 +261,47 @@ def test_argument_errors(ctx):
     with pytest.raises(km.KMeansError) as e:
         km.kmeans_assign(ctx, big, dev(np.ones((2, 300), dtype=np.float32)), prec())
     assert e.value.code == -8
+
+
+# ---------------------------------------------------------------------------
+# Seeding from an earlier assignment (KM_LABELS_HINT) changes nothing
+# ---------------------------------------------------------------------------
+
+def _hint_cases():
+    g = np.random.default_rng(31)
+    X, _, _ = W.blobs(30000, 128, 300, seed=31)
+    C = W.init_centroids(X, 300, 32)
+    yield "blobs128", X, C, km.KM_LOW_FP16
+    Xg, Cg = W.gaussian_pair(20000, 1000, 64, seed=33)
+    yield "gauss64_bf16", Xg, Cg, km.KM_LOW_BF16
+    yield "gauss64_fp32", Xg[:5000], Cg[:300], km.KM_LOW_FP32
+    Xc, Cc = W.cancellation_pair(8000, 64, 16, seed=34)
+    yield "cancel16", Xc, Cc, km.KM_LOW_FP16
+    # duplicated centres (exact ties) in different 32-centre blocks
+    Cd = C.copy()
+    Cd[100:140] = Cd[0:40]
+    yield "duplicates", X[:8000], Cd, km.KM_LOW_FP16
+
+
+@pytest.mark.parametrize("case", list(range(5)))
+def test_labels_hint_gives_identical_results(ctx, case):
+    name, X, C, low = list(_hint_cases())[case]
+    p = prec(low)
+    Xd, Cd = dev(X), dev(C)
+    lab0, md0, sse0, st0 = km.kmeans_assign(ctx, Xd, Cd, p, mindist=True, sse=True)
+    n, k = X.shape[0], C.shape[0]
+    g = np.random.default_rng(case)
+    hints = {
+        "same": host(lab0),
+        "random": g.integers(0, k, size=n).astype(np.int32),
+        "out_of_range": np.where(g.random(n) < 0.5, -3, k + 5).astype(np.int32),
+        "shifted": ((host(lab0) + 1) % k).astype(np.int32),
+    }
+    for hname, h in hints.items():
+        lab = dev(h)
+        _, md, sse, st = km.kmeans_assign(ctx, Xd, Cd, p, labels=lab, mindist=True, sse=True,
+                                          labels_hint=True)
+        np.testing.assert_array_equal(host(lab), host(lab0), err_msg="%s/%s" % (name, hname))
+        np.testing.assert_array_equal(host(md), host(md0))
+        assert float(host(sse)[0]) == float(host(sse0)[0])
+        assert st["n_corrected"] == st0["n_corrected"]
