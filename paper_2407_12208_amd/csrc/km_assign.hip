@@ -576,12 +576,17 @@ k_assign_pipe(const AssignProb* __restrict__ probs, const int32_t* __restrict__ 
 
   // centre tiles, then the saved best blocks [wave][cb][r/4][lane]; before
   // the sweep the same bytes stage the point rows of the prologue
+  // Three tile slots: tile t+1 is in LDS while tile t is processed, so the
+  // fragments and accumulator starts of the next tile's first block are read
+  // before the barrier that ends tile t.  The test constants keep four slots
+  // (the epilogue of a tile's last block runs during the next tile).
+  constexpr int kTileBytes = 3 * CT * LD * (int)sizeof(S);
   constexpr int kSvBytes = kPipeWaves * NB * 4 * 64 * 16;
-  __shared__ __attribute__((aligned(16))) unsigned char lds_main[Cfg::kBytes + kSvBytes];
+  __shared__ __attribute__((aligned(16))) unsigned char lds_main[kTileBytes + kSvBytes];
   unsigned char* const smem = lds_main;
-  f32x4 (*const s_sv)[NB][4][64] = reinterpret_cast<f32x4 (*)[NB][4][64]>(lds_main + Cfg::kBytes);
-  __shared__ float s_cinit[2][CT];
-  __shared__ float s_ca[3][CT];
+  f32x4 (*const s_sv)[NB][4][64] = reinterpret_cast<f32x4 (*)[NB][4][64]>(lds_main + kTileBytes);
+  __shared__ float s_cinit[3][CT];
+  __shared__ float s_ca[4][CT];
   __shared__ int s_q[FALLBACK ? kQueue * NT : 1];
   __shared__ int s_lab[kPipeWaves][NB * 32];
   __shared__ double s_sse[Cfg::kWaves];
@@ -812,7 +817,7 @@ k_assign_pipe(const AssignProb* __restrict__ probs, const int32_t* __restrict__ 
     const int rows = (kpad - t * CT) < CT ? (kpad - t * CT) : CT;
     const int nchunk = rows * DP / Cfg::kElemsPerChunk;
     constexpr int CPR = DP / Cfg::kElemsPerChunk;
-    S* dst = sc0 + (t & 1) * CT * LD;
+    S* dst = sc0 + (t % 3) * CT * LD;
 #pragma unroll
     for (int u = 0; u < Cfg::kChunksPerThread; ++u) {
       const int c = tid + u * NT;
@@ -822,8 +827,8 @@ k_assign_pipe(const AssignProb* __restrict__ probs, const int32_t* __restrict__ 
       }
     }
     if (tid < rows) {
-      s_cinit[t & 1][tid] = st_ci;
-      s_ca[t % 3][tid] = st_ca;
+      s_cinit[t % 3][tid] = st_ci;
+      s_ca[t % 4][tid] = st_ca;
     }
   };
 
@@ -831,7 +836,7 @@ k_assign_pipe(const AssignProb* __restrict__ probs, const int32_t* __restrict__ 
   // K step) from the LDS tile
   typename L::frag af[Cfg::kSteps];
   auto afrag_ptr = [&](int t, int bk) {
-    return sc0 + (t & 1) * CT * LD + (bk * 32 + (lane & 31)) * LD + (lane >> 5) * L::KV;
+    return sc0 + (t % 3) * CT * LD + (bk * 32 + (lane & 31)) * LD + (lane >> 5) * L::KV;
   };
   auto load_af = [&](int t, int bk) {
     const S* arow = afrag_ptr(t, bk);
@@ -847,7 +852,7 @@ k_assign_pipe(const AssignProb* __restrict__ probs, const int32_t* __restrict__ 
   auto issue = [&](f32x16 (&acc)[NB], int t, int bk, bool pre, int tn, int bkn) {
     f32x16 ci;
 #pragma unroll
-    for (int r = 0; r < 16; ++r) ci[r] = s_cinit[t & 1][bk * 32 + acc_row(r, lane)];
+    for (int r = 0; r < 16; ++r) ci[r] = s_cinit[t % 3][bk * 32 + acc_row(r, lane)];
     const S* nrow = afrag_ptr(tn, bkn);
 #pragma unroll
     for (int s = 0; s < Cfg::kSteps; ++s) {
@@ -865,7 +870,7 @@ k_assign_pipe(const AssignProb* __restrict__ probs, const int32_t* __restrict__ 
     if constexpr (FALLBACK) {
       f32x16 cav;
 #pragma unroll
-      for (int r = 0; r < 16; ++r) cav[r] = s_ca[t % 3][bk * 32 + acc_row(r, lane)];
+      for (int r = 0; r < 16; ++r) cav[r] = s_ca[t % 4][bk * 32 + acc_row(r, lane)];
 #pragma unroll
       for (int cb = 0; cb < NB; ++cb) tm[cb] = max16(acc[cb] + cav);
     }
@@ -884,7 +889,7 @@ k_assign_pipe(const AssignProb* __restrict__ probs, const int32_t* __restrict__ 
           uint32_t fm = 0;
 #pragma unroll
           for (int r = 0; r < 16; ++r) {
-            const bool f = w[r] + s_ca[t % 3][bk * 32 + acc_row(r, lane)] >= hx[cb];
+            const bool f = w[r] + s_ca[t % 4][bk * 32 + acc_row(r, lane)] >= hx[cb];
             fm |= (uint32_t)f << r;
             w[r] = f ? -__builtin_inff() : w[r];
           }
@@ -924,7 +929,12 @@ k_assign_pipe(const AssignProb* __restrict__ probs, const int32_t* __restrict__ 
   load_tile(0);
   __syncthreads();  // the staged point rows share these LDS bytes
   store_tile(0);
+  if (1 < ntile) {
+    load_tile(1);
+    store_tile(1);
+  }
   __syncthreads();
+  if (2 < ntile) load_tile(2);
 
   f32x16 accA[NB], accB[NB];
   float tm[NB], wm[NB];
@@ -935,39 +945,42 @@ k_assign_pipe(const AssignProb* __restrict__ probs, const int32_t* __restrict__ 
     __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);         \
     __builtin_amdgcn_sched_group_barrier(0x002, 4, 0);         \
   }
-  // tile 0
-  const int nbk0 = (kpad < CT ? kpad : CT) / 32;
-  if (1 < ntile) load_tile(1);
-  load_af(0, 0);
-  issue(accA, 0, 0, nbk0 == 2, 0, 1);
-  if (nbk0 == 2) {
-    issue(accB, 0, 1, false, 0, 0);
-    epi1(accA, 0, 0, tm, wm);
-    KM_INTERLEAVE();
-    epi2(accA, 0, 0, tm, wm);
-  }
-  if (1 < ntile) store_tile(1);
-  __syncthreads();
-  // tiles 1..: every tile before the last holds two blocks
-  for (int t = 1; t < ntile; ++t) {
-    if (t + 1 < ntile) load_tile(t + 1);
-    const int nbk = ((kpad - t * CT) < CT ? (kpad - t * CT) : CT) / 32;
-    load_af(t, 0);
-    issue(accA, t, 0, nbk == 2, t, 1);
-    epi1(accB, t - 1, 1, tm, wm);
-    KM_INTERLEAVE();
-    epi2(accB, t - 1, 1, tm, wm);
-    if (nbk == 2) {
-      issue(accB, t, 1, false, t, 0);
-      epi1(accA, t, 0, tm, wm);
-      KM_INTERLEAVE();
-      epi2(accA, t, 0, tm, wm);
-    }
-    if (t + 1 < ntile) store_tile(t + 1);
+  // end of tile t: tile t+2 into its slot, barrier, tile t+3 in flight
+  auto tile_end = [&](int t) {
+    if (t + 2 < ntile) store_tile(t + 2);
     if constexpr (FALLBACK) {
       if (__ballot(qn >= kQueue / 2)) flush_queue();  // batch: rare flags wait to the end
     }
     __syncthreads();
+    if (t + 3 < ntile) load_tile(t + 3);
+  };
+  // block 1 of tile t prefetches block 0 of tile t+1 (already in LDS); the
+  // last tile prefetches a block of its own (unused)
+  // tile 0
+  const int nbk0 = (kpad < CT ? kpad : CT) / 32;
+  load_af(0, 0);
+  issue(accA, 0, 0, true, 0, 1);  // a tile of one block prefetches unused rows
+  if (nbk0 == 2) {
+    issue(accB, 0, 1, true, 1 < ntile ? 1 : 0, 0);
+    epi1(accA, 0, 0, tm, wm);
+    KM_INTERLEAVE();
+    epi2(accA, 0, 0, tm, wm);
+  }
+  tile_end(0);
+  // tiles 1..: every tile before the last holds two blocks
+  for (int t = 1; t < ntile; ++t) {
+    const int nbk = ((kpad - t * CT) < CT ? (kpad - t * CT) : CT) / 32;
+    issue(accA, t, 0, true, t, 1);
+    epi1(accB, t - 1, 1, tm, wm);
+    KM_INTERLEAVE();
+    epi2(accB, t - 1, 1, tm, wm);
+    if (nbk == 2) {
+      issue(accB, t, 1, true, t + 1 < ntile ? t + 1 : t, 0);
+      epi1(accA, t, 0, tm, wm);
+      KM_INTERLEAVE();
+      epi2(accA, t, 0, tm, wm);
+    }
+    tile_end(t);
   }
 #undef KM_INTERLEAVE
   {
