@@ -880,11 +880,20 @@ k_assign_pipe(const AssignProb* __restrict__ probs, const int32_t* __restrict__ 
   // epilogue part 2: rare slow path for flagged pairs, then the running best
   auto epi2 = [&](const f32x16 (&acc)[NB], int t, int bk, float (&tm)[NB], float (&wm)[NB]) {
     const int jb = t * CT + bk * 32;
+    // the block's values go to LDS when it improves the running best; each
+    // path stores from its own registers (no merged copy of the block)
+    auto save = [&](int cb, const f32x16& w) {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        f32x4 v = {w[4 * q], w[4 * q + 1], w[4 * q + 2], w[4 * q + 3]};
+        s_sv[wave][cb][q][lane] = v;
+      }
+    };
 #pragma unroll
     for (int cb = 0; cb < NB; ++cb) {
-      f32x16 w = acc[cb];
       if constexpr (FALLBACK) {
         if (__builtin_expect(__ballot(tm[cb] >= hx[cb]) != 0, 0)) {  // rare, wave-uniform
+          f32x16 w = acc[cb];
           const int pl = pw + cb * 32 + (lane & 31);
           uint32_t fm = 0;
 #pragma unroll
@@ -912,16 +921,18 @@ k_assign_pipe(const AssignProb* __restrict__ probs, const int32_t* __restrict__ 
               }
             }
           }
+          if (wm[cb] > bw[cb]) {  // strict: the earlier block keeps ties
+            bw[cb] = wm[cb];
+            bb[cb] = jb;
+            save(cb, w);
+          }
+          continue;
         }
       }
-      if (wm[cb] > bw[cb]) {  // strict: the earlier block keeps ties
+      if (wm[cb] > bw[cb]) {
         bw[cb] = wm[cb];
         bb[cb] = jb;
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          f32x4 v = {w[4 * q], w[4 * q + 1], w[4 * q + 2], w[4 * q + 3]};
-          s_sv[wave][cb][q][lane] = v;
-        }
+        save(cb, acc[cb]);
       }
     }
   };

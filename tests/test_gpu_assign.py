@@ -305,3 +305,56 @@ def test_labels_hint_gives_identical_results(ctx, case):
         np.testing.assert_array_equal(host(md), host(md0))
         assert float(host(sse)[0]) == float(host(sse0)[0])
         assert st["n_corrected"] == st0["n_corrected"]
+
+
+# ---------------------------------------------------------------------------
+# Exact ties between centres of different norms, and large k
+# ---------------------------------------------------------------------------
+
+def _tie_case(i_a, i_b, k, d=128):
+    """Points x = e1 and two centres 12 e1 (index i_a, norm 144) and -10 e1
+    (index i_b, norm 100) with the same W = x.c - |c|^2/2 = -60 exactly (both
+    pairs are kept by the test, d^ = 121); the other centres are far away.
+    The lower index must win wherever the two sit (same or different
+    32-centre blocks, either order)."""
+    n = 1000
+    X = np.zeros((n, d), dtype=np.float32)
+    X[:, 0] = 1.0
+    C = np.zeros((k, d), dtype=np.float32)
+    for j in range(k):
+        C[j, 1 + j % (d - 1)] = 100.0
+    C[i_a] = 0.0
+    C[i_a, 0] = 12.0
+    C[i_b] = 0.0
+    C[i_b, 0] = -10.0
+    return X, C
+
+
+@pytest.mark.parametrize("low", [km.KM_LOW_FP16, km.KM_LOW_BF16])
+@pytest.mark.parametrize("i_a,i_b,k", [(3, 150, 200), (150, 3, 200), (0, 1, 2), (1, 0, 2),
+                                       (4099, 5, 4100), (33, 32, 64)])
+def test_equal_maxima_of_different_norms_pick_lowest_index(ctx, low, i_a, i_b, k):
+    X, C = _tie_case(i_a, i_b, k)
+    p = prec(low)
+    labels, mind, sse, st = _run_assign(ctx, X, C, p)
+    assert st["data_status"] == 0
+    assert np.all(labels == min(i_a, i_b))
+    assert np.all(mind == 121.0)
+    n = X.shape[0]
+    # seeded with the tied centre of the larger index, or with random labels
+    for h in (np.full(n, max(i_a, i_b), dtype=np.int32),
+              np.random.default_rng(k).integers(0, k, size=n).astype(np.int32)):
+        lab = dev(h)
+        km.kmeans_assign(ctx, dev(X), dev(C), p, labels=lab, labels_hint=True)
+        assert np.all(host(lab) == min(i_a, i_b))
+
+
+@pytest.mark.parametrize("k,d", [(4100, 16), (9000, 8), (4096, 32)])
+def test_assign_many_centres(ctx, k, d):
+    # k of several thousand centres with a ragged last 64-centre tile (4100)
+    Xg, Cg = W.gaussian_pair(1500, k, d, seed=k + d)
+    for low, fmt in ((km.KM_LOW_FP16, 0), (km.KM_LOW_BF16, 1)):
+        labels, mind, sse, st = _run_assign(ctx, Xg, Cg, prec(low))
+        assert st["data_status"] == 0
+        check_assignment(Xg, Cg, fmt, st["alpha_used"], labels, mind, sse, st["n_corrected"],
+                         min_coverage=0.95)
