@@ -13,8 +13,12 @@ resident in HBM before timing starts.
 
 Prints ONE JSON line.  Extra keys report the assignment kernel alone, the
 plain FP64 direct-formula kernel on the same input, the fallback ratio, the
-single-solve Lloyd rate (20,000 x 32, k = 16) and, as `cpu_baseline`, the
-CPU oracle timed on a bounded sample of the same workload.
+single-solve Lloyd rate (20,000 x 32, k = 16), the large clustering
+(2,000,000 x 64, 1,024 blobs, 50 rounds) in BF16/FP16 -> FP64, uniform FP32
+and plain FP64, the batched segmentation-shaped instances (256 problems, one
+batched solve against one solve per problem), serving, and, as
+`cpu_baseline`, the CPU oracle timed on a bounded sample of the same
+workload.
 """
 
 import argparse
@@ -131,6 +135,93 @@ def measured_traffic():
         return None
 
 
+def large_bench(km, ctx, torch, W, np):
+    """Large clustering: 2,000,000 x 64 points from 1,024 blobs (centres
+    U[-50,50]^64, per-blob std log-uniform in [0.1, 2]), 50 Lloyd rounds and
+    the final pass per variant, from the same initial centres."""
+    cfg = W.LLOYD_LARGE
+    log("large clustering: generating %d x %d, %d blobs" % (cfg["n"], cfg["d"], cfg["k"]))
+    X, _, _ = W.blobs(cfg["n"], cfg["d"], cfg["k"], cfg["seed"], center_box=(-50, 50),
+                      std_range=(0.1, 2.0))
+    C0 = W.init_centroids(X, cfg["k"], cfg["init_seed"])
+    Xd = torch.from_numpy(X).cuda()
+    del X
+    iters = cfg["iters"]
+    out = {"n": cfg["n"], "d": cfg["d"], "k": cfg["k"], "rounds": iters}
+    variants = (("bf16_fp64", km.Precision(km.KM_LOW_BF16)),
+                ("fp16_fp64", km.Precision(km.KM_LOW_FP16)),
+                ("fp32_uniform", km.Precision(km.KM_LOW_FP32, km.KM_ALPHA_NONE)),
+                ("fp64_direct", km.Precision(km.KM_EXACT64)))
+    for name, pr in variants:
+        C = torch.from_numpy(C0).cuda()
+        km.kmeans_lloyd(ctx, Xd, C, 1, prec=pr, stats=False, sync=True)  # workspace
+        C.copy_(torch.from_numpy(C0).cuda())
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, _, _, hist, st = km.kmeans_lloyd(ctx, Xd, C, iters, prec=pr, sse_hist=True,
+                                            stats=True, sync=True)
+        dt = time.perf_counter() - t0
+        out[name] = {"rounds_per_s": iters / dt, "ms_per_round": 1e3 * dt / (iters + 1),
+                     "eta": st["n_corrected"] / max(st["n_pairs"], 1),
+                     "final_sse": float(hist[-1].item())}
+        log("large %s: %.3f ms per round, eta %.3g" % (name, out[name]["ms_per_round"],
+                                                         out[name]["eta"]))
+    out["speedup_fp16_fp64_vs_fp64_direct"] = (out["fp16_fp64"]["rounds_per_s"] /
+                                               out["fp64_direct"]["rounds_per_s"])
+    return out
+
+
+def batch_bench(km, ctx, torch, W, np, count=256, iters=30):
+    """Batched segmentation-shaped instances: `count` problems (n = H*W
+    pixels, H, W ~ U{128..1024}, d = 5 features, k ~ U{4..64}), `iters` rounds
+    each, FP16 -> FP64: one batched solve against one Lloyd call per problem
+    on the same inputs.  Labels of the two runs are compared."""
+    log("batched: generating %d segmentation-shaped instances" % count)
+    insts = W.segmentation_batch(count, 3004)
+    Xs = [torch.from_numpy(b["X"]).cuda() for b in insts]
+    C0s = [torch.from_numpy(b["C0"]).cuda() for b in insts]
+    total_n = sum(b["X"].shape[0] for b in insts)
+    d = insts[0]["X"].shape[1]
+    del insts
+    prec = km.Precision(km.KM_LOW_FP16)
+
+    def batched():
+        items = [km.BatchItem(X=X, C=C0.clone(), max_iter=iters) for X, C0 in zip(Xs, C0s)]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        km.kmeans_solve_batch(ctx, items, prec, with_sse=False)
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0, [it.labels for it in items]
+
+    def one_by_one():
+        Cs = [C0.clone() for C0 in C0s]
+        labs = [torch.empty(X.shape[0], dtype=torch.int32, device="cuda") for X in Xs]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for X, C, lab in zip(Xs, Cs, labs):
+            km.kmeans_lloyd(ctx, X, C, iters, prec=prec, labels=lab, stats=False)
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0, labs
+
+    batched()
+    one_by_one()
+    tb, lb = batched()
+    ts, ls = one_by_one()
+    same = all(bool(torch.equal(a, b)) for a, b in zip(lb, ls))
+    passes = iters + 1
+    # algorithmic bytes of an assignment pass: read X once, write the labels
+    alg_bytes = float(total_n) * (4 * d + 4) * passes
+    out = {"problems": count, "points": total_n, "d": d, "rounds": iters,
+           "batched_s": tb, "one_by_one_s": ts, "speedup": ts / tb,
+           "batched_solves_per_s": count / tb, "one_by_one_solves_per_s": count / ts,
+           "labels_identical": same,
+           "batched_assign_bytes_GBps": alg_bytes / tb / 1e9,
+           "batched_frac_of_hbm_peak": alg_bytes / tb / 1e9 / HBM_PEAK_GBS}
+    log("batched: %.1f ms batched, %.1f ms one by one, labels identical %s" %
+        (1e3 * tb, 1e3 * ts, same))
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -139,6 +230,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-extra", action="store_true", help="skip the extra measurements")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--batch-problems", type=int, default=256,
+                    help="problems in the batched measurement (0 = skip)")
     ap.add_argument("--serve-requests", type=int, default=48,
                     help="requests in the serving measurement (0 = skip)")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
@@ -267,6 +360,10 @@ def main():
             res[name] = cs["iters"] / dt
         extra["lloyd_small_iters_per_s"] = res["mixed_fp16_fp64"]
         extra["lloyd_small_iters_per_s_fp64_direct"] = res["fp64_direct"]
+        extra["large_clustering"] = large_bench(km, ctx, torch, W, np)
+        if args.batch_problems > 0:
+            extra["batched_segmentation"] = batch_bench(km, ctx, torch, W, np,
+                                                        count=args.batch_problems)
         if args.serve_requests > 0:
             extra["serving"] = serve_bench(km, ctx, args.serve_requests, 3005)
         out["extra"] = extra

@@ -182,23 +182,22 @@ def segmentation_instance(seed: int, *, H=None, W=None, hw_range=(128, 1024),
     M = int(g.integers(modes_range[0], modes_range[1] + 1))
     colors = g.uniform(0.0, 1.0, size=(M, 3))
     seeds = np.stack([g.uniform(0, H, size=M), g.uniform(0, W, size=M)], axis=1)
-    yy, xx = np.meshgrid(np.arange(H, dtype=np.float64),
-                         np.arange(W, dtype=np.float64), indexing="ij")
+    yy = np.arange(H, dtype=np.float64)[:, None]
+    xx = np.arange(W, dtype=np.float64)[None, :]
     best = np.full((H, W), np.inf)
     region = np.zeros((H, W), dtype=np.int64)
-    for s in range(M):
+    for s in range(M):  # nearest seed, the first one on ties
         dd = (yy - seeds[s, 0]) ** 2 + (xx - seeds[s, 1]) ** 2
-        closer = dd < best
-        best[closer] = dd[closer]
-        region[closer] = s
+        region = np.where(dd < best, s, region)
+        np.minimum(best, dd, out=best)
     rgb = colors[region] + noise * g.standard_normal(size=(H, W, 3))
     rgb = np.clip(rgb, 0.0, 1.0)
     out = g.uniform(0.0, 1.0, size=(H, W)) < outlier_frac
     rgb[out] = g.uniform(0.0, 1.0, size=(int(out.sum()), 3))
     feats = np.concatenate(
         [rgb.reshape(-1, 3),
-         (xx / max(W - 1, 1)).reshape(-1, 1),
-         (yy / max(H - 1, 1)).reshape(-1, 1)], axis=1)
+         np.broadcast_to(xx / max(W - 1, 1), (H, W)).reshape(-1, 1),
+         np.broadcast_to(yy / max(H - 1, 1), (H, W)).reshape(-1, 1)], axis=1)
     lo = feats.min(axis=0)
     span = feats.max(axis=0) - lo
     span[span == 0] = 1.0
