@@ -6,6 +6,7 @@
 
 #include <algorithm>
 #include <new>
+#include <map>
 #include <vector>
 
 #include "km_context.hpp"
@@ -106,6 +107,17 @@ size_t cq_elem_bytes(int low) { return low == kLowFP32 ? 4 : 2; }
 // pass is run by the FP64 direct kernel instead of a fully divergent sweep.
 static constexpr double kDenseAlpha = 2.5;
 
+// Groups of 32 points per wave of the small-problem kernel: the centre
+// set-up of a workgroup is amortised over more points once the launch
+// (`launch_points` over all of its problems) still has >= 4096 workgroups.
+void set_small_sweep(AssignPlan& a, int64_t n, int64_t launch_points) {
+  if (a.xd <= 0) return;
+  const int64_t q = launch_points / ((int64_t)kSmallWaves * 32 * 4096);
+  a.gpw = q >= 8 ? 8 : q >= 4 ? 4 : q >= 2 ? 2 : 1;
+  const int64_t ppw = (int64_t)kSmallWaves * 32 * a.gpw;
+  a.nwg = (int)((n + ppw - 1) / ppw);
+}
+
 AssignPlan plan_assign(const km_precision& p, int64_t n, int d, int k) {
   AssignPlan a{};
   a.low = p.low;
@@ -131,6 +143,12 @@ AssignPlan plan_assign(const km_precision& p, int64_t n, int d, int k) {
   } else {
     a.nwg = (int)((n + assign_points_per_wg(p.low, a.DP) - 1) / assign_points_per_wg(p.low, a.DP));
     a.nwg_pair = (int)((n + mfma_points_per_wg(p.low, a.DP) - 1) / mfma_points_per_wg(p.low, a.DP));
+    // few coordinates and centres: the pass is bound by memory and the
+    // vector epilogue, and a lighter kernel with resident centres serves it
+    if ((p.low == KM_LOW_FP16 || p.low == KM_LOW_BF16) && d <= kSmallMaxD && a.k_pad <= kSmallMaxK) {
+      a.xd = small_xd(d);
+      set_small_sweep(a, n, n);
+    }
   }
   return a;
 }
@@ -218,6 +236,11 @@ static hipError_t run_assign_dev(km_context_impl* ctx, const AssignPlan& shape, 
   switch (shape.route) {
     case Route::Mfma:
     case Route::MfmaNoFallback:
+      if (mode == 0 && shape.xd > 0) {
+        e = launch_assign_small(shape.low, shape.xd, shape.route == Route::Mfma, (const AssignProb*)dp,
+                                (const int32_t*)ds, nprob, total_wg, st);
+        break;
+      }
       e = launch_assign_mfma(shape.low, shape.DP, mode, shape.route == Route::Mfma, (const AssignProb*)dp,
                              (const int32_t*)ds, nprob, total_wg, st);
       break;
@@ -268,6 +291,7 @@ UpdateProb carve_update(Arena& a, int64_t n, int d, int k) {
   u.d = d;
   u.k = k;
   u.ntiles = ntiles;
+  u.chunk = upd_chunk(d);
   return u;
 }
 
@@ -277,7 +301,7 @@ hipError_t run_update(km_context_impl* ctx, const std::vector<UpdateProb>& probs
   for (int i = 0; i < np; ++i) {
     tiles[i] = probs[i].ntiles;
     cl[i] = probs[i].k;
-    chunkwg[i] = (int)(((probs[i].n + kUpdChunk - 1) / kUpdChunk + probs[i].k + 3) / 4);
+    chunkwg[i] = (int)(((probs[i].n + probs[i].chunk - 1) / probs[i].chunk + probs[i].k + 3) / 4);
     clwg[i] = (probs[i].k + 3) / 4;
     scatwg[i] = (probs[i].ntiles + 3) / 4;
   }
@@ -481,6 +505,7 @@ static hipError_t enqueue_pass(km_context_impl* ctx, const AssignPlan& a, const 
   ap.oma = a.oma;
   ap.refine = refine ? 1 : 0;
   ap.hint = hint ? labels : nullptr;
+  ap.gpw = a.gpw;
   const int nwg = mode == 0 ? a.nwg : a.nwg_pair;
   const int32_t apre[2] = {0, nwg};
   const size_t o_ap = pk.add(&ap, sizeof(ap));
@@ -725,7 +750,7 @@ hipError_t enqueue_batch_pass(km_context_impl* ctx, std::vector<BatchState*>& li
     std::vector<int> nw;
     for (size_t j = i; j < list.size(); ++j) {
       const AssignPlan& o = list[j]->plan;
-      if (taken[j] || o.route != sh.route || o.DP != sh.DP || o.low != sh.low) continue;
+      if (taken[j] || o.route != sh.route || o.DP != sh.DP || o.low != sh.low || o.xd != sh.xd) continue;
       taken[j] = true;
       BatchState* s = list[j];
       AssignProb a{};
@@ -746,6 +771,7 @@ hipError_t enqueue_batch_pass(km_context_impl* ctx, std::vector<BatchState*>& li
       a.oma = o.oma;
       a.refine = final_pass ? 1 : 0;
       a.hint = s->it > 0 ? s->prob->labels : nullptr;  // the previous round's labels
+      a.gpw = o.gpw;
       ap.push_back(a);
       nw.push_back(o.nwg);
     }
@@ -812,6 +838,15 @@ extern "C" int32_t kmeans_solve_batch(km_context* ctx, km_problem* probs, int32_
   for (int i = 0; i < count; ++i) {
     S[i].prob = &probs[i];
     S[i].plan = plan_assign(p, probs[i].n, probs[i].d, probs[i].k);
+  }
+  {  // problems sharing a small-problem launch: sweep length from their total
+    std::map<int, int64_t> total;
+    for (int i = 0; i < count; ++i)
+      if (S[i].plan.xd > 0) total[S[i].plan.xd] += probs[i].n;
+    for (int i = 0; i < count; ++i)
+      if (S[i].plan.xd > 0) set_small_sweep(S[i].plan, probs[i].n, total[S[i].plan.xd]);
+  }
+  for (int i = 0; i < count; ++i) {
     plan_pass(pl, S[i].plan);
     plan_update(pl, probs[i].n, probs[i].d, probs[i].k);
     pl.add<float>((size_t)probs[i].k * probs[i].d);

@@ -1074,6 +1074,337 @@ k_assign_pipe(const AssignProb* __restrict__ probs, const int32_t* __restrict__ 
 }
 
 // ---------------------------------------------------------------------------
+// Fused mixed-precision assignment for small problems (d <= 32, k <= 64).
+//
+// Same arithmetic and outputs as k_assign_pipe in assignment mode, for shapes
+// that are bound by memory and the vector epilogue rather than the matrix
+// cores (a few coordinates, a few dozen centres).  The centres' fragments
+// (at most two 32-centre blocks) stay in registers for the whole launch, their
+// accumulator starts and test constants in LDS, and each wave sweeps `gpw` groups of 32 points, loading
+// the rows of the next group before the epilogue of the current one.  Every
+// lane holds the full FP32 row of its point (the two lanes of a point hold
+// different centres of a block).  Flagged pairs can be frequent on such data
+// (a tenth of all pairs on normalised image features), so they are not
+// corrected by their own lane: the lanes append them to a per-wave queue in
+// LDS (positions from a prefix sum of the lanes' counts) and all 64 lanes
+// evaluate the FP64 direct formula on the queue, merging each result into its
+// point's best corrected pair with a 64-bit LDS minimum on (FP32 value bits,
+// centre index) -- smallest value, then lowest index, as in a sequential
+// scan.
+//   XD: register capacity of a point row (8, 16 or 32, >= d)
+// The reliability test first adds the lane's block maximum of W and the
+// largest centre term of its rows: FP32 addition is monotonic, so when that
+// sum stays below the threshold no pair of the lane is flagged, exactly as
+// the per-pair test "W + ca_j >= hx" would decide.  Otherwise the per-pair
+// test masks the flagged pairs and queues them.
+// ---------------------------------------------------------------------------
+// Orders this wave's LDS accesses: LDS operations of one wave complete in
+// issue order; the fence keeps the compiler from moving accesses across it
+// and the wait makes the results of earlier ones visible to every lane.
+__device__ inline void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_s_waitcnt(0xc07f);  // lgkmcnt(0)
+  __builtin_amdgcn_wave_barrier();
+}
+
+template <int XD>
+__device__ inline double sqdist64_rl(const float (&x)[XD], const float* c, int d) {
+  double s = 0.0;
+#pragma unroll
+  for (int l = 0; l < XD; ++l) {
+    if (l >= d) break;
+    const double e = (double)x[l] - (double)c[l];
+    s = __builtin_fma(e, e, s);
+  }
+  return s;
+}
+
+template <class L, int XD, bool FALLBACK>
+__global__ void __launch_bounds__(kSmallThreads, XD == 8 ? 4 : XD == 16 ? 3 : 2)
+k_assign_small(const AssignProb* __restrict__ probs, const int32_t* __restrict__ wg_start, int nprob) {
+  constexpr int DP = XD < 16 ? 16 : XD;  // row extent of the quantised centres
+  constexpr int STEPS = DP / L::KS;
+  constexpr int CS = XD + 1;             // LDS row stride of the FP32 centres
+  using S = typename L::S;
+  using frag = typename L::frag;
+  __shared__ float s_ca[kSmallMaxK];
+  __shared__ __attribute__((aligned(16))) float s_cinit[kSmallMaxK];
+  __shared__ float s_c[kSmallMaxK * CS];
+  // correction queue of a 32-centre block (at most 32 x 32 pairs), the
+  // group's point rows and each point's best corrected pair
+  __shared__ int s_q[FALLBACK ? kSmallWaves : 1][FALLBACK ? 32 * 32 : 1];
+  __shared__ float s_x[FALLBACK ? kSmallWaves : 1][FALLBACK ? 32 * CS : 1];
+  __shared__ unsigned long long s_key[FALLBACK ? kSmallWaves : 1][32];
+  __shared__ double s_sse[kSmallWaves];
+  __shared__ unsigned long long s_corr[kSmallWaves];
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int hi = lane >> 5;
+  const int pi = find_problem(wg_start, nprob, blockIdx.x);
+  const AssignProb& P = probs[pi];
+  const int tile = blockIdx.x - wg_start[pi];
+  const int gpw = P.gpw;
+  const int64_t p0 = (int64_t)tile * (kSmallWaves * 32) * gpw;
+  const int64_t n = P.n;
+  const int d = P.d;
+  const int k = P.k;
+  const int kb = P.k_pad > 32 ? 2 : 1;
+
+  const bool vec4 = ((d & 3) == 0) && ((((uintptr_t)P.X) & 15) == 0);
+  auto load_rows = [&](int q, float (&xr)[XD]) {
+    const int64_t p = p0 + (int64_t)(q * kSmallWaves + wave) * 32 + (lane & 31);
+    const bool pv = p < n;
+    const KM_GLOBAL float* row = as_global(P.X) + (pv ? p : 0) * d;
+    if (vec4) {
+#pragma unroll
+      for (int l = 0; l < XD; l += 4) {
+        f32x4 v = {0.f, 0.f, 0.f, 0.f};
+        if (l < d) v = *reinterpret_cast<const KM_GLOBAL f32x4*>(row + l);
+        xr[l] = v[0]; xr[l + 1] = v[1]; xr[l + 2] = v[2]; xr[l + 3] = v[3];
+      }
+    } else {
+#pragma unroll
+      for (int l = 0; l < XD; ++l) xr[l] = l < d ? row[l] : 0.0f;
+    }
+#pragma unroll
+    for (int l = 0; l < XD; ++l) xr[l] = pv ? xr[l] : 0.0f;
+  };
+  // the first group's rows are requested before the centre set-up
+  float xn[XD];
+  load_rows(0, xn);
+
+  // FP32 centres (corrections, refinement) and test constants to LDS
+  for (int e = tid; e < kSmallMaxK * CS; e += kSmallThreads) {
+    const int j = e / CS, l = e - j * CS;
+    s_c[e] = (j < k && l < d) ? as_global(P.C)[(int64_t)j * d + l] : 0.0f;
+  }
+  if (tid < kSmallMaxK) {
+    s_ca[tid] = tid < P.k_pad ? as_global(P.ca)[tid] : 0.0f;
+    s_cinit[tid] = tid < P.k_pad ? as_global(P.cinit)[tid] : -__builtin_inff();
+  }
+
+  // centre fragments in registers (accumulator starts in LDS)
+  const KM_GLOBAL S* Cq = reinterpret_cast<const KM_GLOBAL S*>(as_global(P.Cq));
+  frag af[2][STEPS];
+#pragma unroll
+  for (int b = 0; b < 2; ++b) {
+#pragma unroll
+    for (int s = 0; s < STEPS; ++s)
+      af[b][s] = b < kb ? *reinterpret_cast<const KM_GLOBAL frag*>(Cq + (int64_t)(b * 32 + (lane & 31)) * DP +
+                                                                 s * L::KS + hi * L::KV)
+                        : frag{};
+  }
+  // accumulator start of block b: -nc_j/2 of the lane's rows
+  auto acc_start = [&](int b) {
+    f32x16 a;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const f32x4 v = *reinterpret_cast<const f32x4*>(&s_cinit[b * 32 + 8 * q + 4 * hi]);
+      a[4 * q] = v[0]; a[4 * q + 1] = v[1]; a[4 * q + 2] = v[2]; a[4 * q + 3] = v[3];
+    }
+    return a;
+  };
+  __syncthreads();
+  // rows of real centres among the lane's rows of each block
+  uint32_t vmask[2];
+#pragma unroll
+  for (int b = 0; b < 2; ++b) {
+    uint32_t v = 0;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) v |= (uint32_t)(b * 32 + acc_row(r, lane) < k) << r;
+    vmask[b] = v;
+  }
+  float cam[2];
+#pragma unroll
+  for (int b = 0; b < 2; ++b) {
+    float m = -__builtin_inff();
+#pragma unroll
+    for (int r = 0; r < 16; ++r) m = __builtin_fmaxf(m, s_ca[b * 32 + acc_row(r, lane)]);
+    cam[b] = m;
+  }
+
+  int bad = 0;
+  double sse = 0.0;
+  unsigned long long ncorr = 0;
+  for (int q = 0; q < gpw; ++q) {
+    float x[XD];
+#pragma unroll
+    for (int l = 0; l < XD; ++l) x[l] = xn[l];
+    if (q + 1 < gpw) load_rows(q + 1, xn);
+    const int64_t p = p0 + (int64_t)(q * kSmallWaves + wave) * 32 + (lane & 31);
+    const bool pv = p < n;
+
+    // range and finiteness, rounding, quantised norm (coordinates in order)
+    S qx[XD];
+    float nxv = 0.0f;
+#pragma unroll
+    for (int l = 0; l < XD; ++l) {
+      qx[l] = L::cvt(x[l]);
+      if (l < d) {
+        if (!__builtin_isfinite(x[l])) bad |= kStatusNonFinite;
+        if (L::kHasRange && __builtin_fabsf(x[l]) >= L::kOverflow) bad |= kStatusRange;
+        const float f = L::tof(qx[l]);
+        nxv = __builtin_fmaf(f, f, nxv);
+      }
+    }
+    frag bf[STEPS];
+#pragma unroll
+    for (int s = 0; s < STEPS; ++s) {
+#pragma unroll
+      for (int u = 0; u < L::KV; ++u) {
+        const int l0 = s * L::KS + u, l1 = s * L::KS + L::KV + u;
+        const S a = l0 < XD ? qx[l0] : S(0.0f);
+        const S c = l1 < XD ? qx[l1] : S(0.0f);
+        bf[s][u] = hi ? c : a;
+      }
+    }
+    const float hx = pv ? 0.5f * (P.oma * nxv) : __builtin_inff();
+
+    // cross terms W = x~^T c~ - nc/2 of both blocks
+    f32x16 acc[2];
+    float m[2];
+    acc[0] = acc_start(0);
+#pragma unroll
+    for (int s = 0; s < STEPS; ++s) acc[0] = L::mfma(af[0][s], bf[s], acc[0]);
+    // a second block is always issued: without centres its fragments are
+    // zero and its starts -inf, so it never wins and is never flagged
+    acc[1] = acc_start(1);
+#pragma unroll
+    for (int s = 0; s < STEPS; ++s) acc[1] = L::mfma(af[1][s], bf[s], acc[1]);
+    m[0] = max16(acc[0]);
+    m[1] = max16(acc[1]);
+
+    // reliability test; flagged pairs go to the wave's queue and are
+    // corrected in FP64 by all lanes together
+    bool staged = false;
+    if constexpr (FALLBACK) {
+#pragma unroll
+      for (int b = 0; b < 2; ++b) {
+        if (b >= kb) break;
+        if (__ballot(m[b] + cam[b] >= hx) != 0) {
+          uint32_t fm = 0;
+#pragma unroll
+          for (int r = 0; r < 16; ++r) {
+            const bool f = acc[b][r] + s_ca[b * 32 + acc_row(r, lane)] >= hx;
+            fm |= (uint32_t)f << r;
+            acc[b][r] = f ? -__builtin_inff() : acc[b][r];
+          }
+          m[b] = max16(acc[b]);
+          fm &= vmask[b];
+          if (!staged) {  // the group's rows and best corrected pairs
+            staged = true;
+            if (hi == 0) {
+#pragma unroll
+              for (int l = 0; l < XD; ++l)
+                if (l < d) s_x[wave][(lane & 31) * CS + l] = x[l];
+              s_key[wave][lane & 31] = ~0ull;
+            }
+          }
+          // queue positions: exclusive prefix of the lanes' flag counts
+          // (at most 16), one ballot per bit of the count
+          const int cnt = __builtin_popcount(fm);
+          int pos = 0, total = 0;
+#pragma unroll
+          for (int bit = 0; bit < 5; ++bit) {
+            const unsigned long long bal = __ballot((cnt >> bit) & 1);
+            const int below = (int)__builtin_amdgcn_mbcnt_hi((unsigned)(bal >> 32),
+                                                             __builtin_amdgcn_mbcnt_lo((unsigned)bal, 0u));
+            pos += below << bit;
+            total += __popcll(bal) << bit;
+          }
+          while (fm) {
+            const int r = __builtin_ctz(fm);
+            fm &= fm - 1;
+            s_q[wave][pos++] = (lane & 31) | ((b * 32 + acc_row(r, lane)) << 5);
+          }
+          wave_lds_sync();
+          for (int e = lane; e < total; e += 64) {
+            const int code = s_q[wave][e];
+            const int pt = code & 31, j = code >> 5;
+            const float* xr = &s_x[wave][pt * CS];
+            const float* cr = &s_c[j * CS];
+            double sq = 0.0;
+#pragma unroll
+            for (int l = 0; l < XD; ++l) {
+              if (l >= d) break;
+              const double t = (double)xr[l] - (double)cr[l];
+              sq = __builtin_fma(t, t, sq);
+            }
+            // smallest value, then lowest index: FP32 bits of a
+            // non-negative value order like the value
+            const unsigned long long key =
+                ((unsigned long long)__float_as_uint((float)sq) << 32) | (unsigned)j;
+            atomicMin(&s_key[wave][pt], key);
+            ncorr += 1;
+          }
+          wave_lds_sync();
+        }
+      }
+    }
+    float cd = __builtin_inff();
+    int cj = -1;
+    if (staged) {
+      const unsigned long long key = s_key[wave][lane & 31];
+      if (key != ~0ull) {
+        cj = (int)(key & 0xffffffffu);
+        cd = __uint_as_float((unsigned)(key >> 32));
+      }
+    }
+
+    // best kept pair of the lane: block, then the lowest row holding it
+    const bool sel = m[1] > m[0];
+    float bw = sel ? m[1] : m[0];
+    int rs = 16;
+#pragma unroll
+    for (int r = 15; r >= 0; --r) {
+      const float v = sel ? acc[1][r] : acc[0][r];
+      rs = (v == bw) ? r : rs;
+    }
+    int bj = (bw > -__builtin_inff() && rs < 16) ? (sel ? 32 : 0) + acc_row(rs, lane) : -1;
+    // merge the two lanes of the point; choose between kept and corrected
+    const float ow = __shfl_xor(bw, 32, kWave);
+    const int oj = __shfl_xor(bj, 32, kWave);
+    if (ow > bw || (ow == bw && oj >= 0 && (bj < 0 || oj < bj))) {
+      bw = ow;
+      bj = oj;
+    }
+    if (hi == 0 && pv) {
+      const float dk = bj >= 0 ? __builtin_fmaxf(nxv - 2.0f * bw, 0.0f) : __builtin_inff();
+      int lab = bj;
+      if (cj >= 0 && (cd < dk || (cd == dk && cj < lab) || lab < 0)) lab = cj;
+      if (lab < 0 || lab >= k) lab = 0;  // only with non-finite data (status raised)
+      as_global(P.labels)[p] = lab;
+      if (P.refine) {
+        const double dd = sqdist64_rl<XD>(x, s_c + lab * CS, d);
+        if (P.mindist) as_global(P.mindist)[p] = (float)dd;
+        sse += dd;
+      }
+    }
+  }
+  raise_status(P.status, bad);
+  sse = wave_sum(sse);
+  const unsigned long long nc = wave_sum_u64(ncorr);
+  if (lane == 0) {
+    s_sse[wave] = sse;
+    s_corr[wave] = nc;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    double ssum = 0.0;
+    unsigned long long c = 0;
+#pragma unroll
+    for (int w = 0; w < kSmallWaves; ++w) {
+      ssum += s_sse[w];
+      c += s_corr[w];
+    }
+    as_global(P.sse_part)[tile] = ssum;
+    as_global(P.corr_part)[tile] = c;
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Every pair by the FP64 direct formula.  64 points x 64 centres per step,
 // 256 threads each owning a 4 x 4 block of pairs; FP32 tiles in LDS.
 // CMP64: compare the FP64 values (plain FP64 kernel); otherwise compare the
@@ -1325,6 +1656,36 @@ hipError_t launch_assign_mfma(int low, int DP, int mode, bool fallback, const As
     case kLowBF16: return launch_mfma_l<LowBF16>(DP, mode, fallback, dprobs, dstart, nprob, nwg, st);
     case kLowFP32: return launch_mfma_l<LowF32>(DP, mode, fallback, dprobs, dstart, nprob, nwg, st);
   }
+  return hipErrorInvalidValue;
+}
+
+template <class L, bool FALLBACK>
+static hipError_t launch_small_t(int xd, const AssignProb* dprobs, const int32_t* dstart, int nprob, int nwg,
+                                 hipStream_t st) {
+  switch (xd) {
+    case 8:
+      hipLaunchKernelGGL((k_assign_small<L, 8, FALLBACK>), dim3(nwg), dim3(kSmallThreads), 0, st, dprobs, dstart, nprob);
+      break;
+    case 16:
+      hipLaunchKernelGGL((k_assign_small<L, 16, FALLBACK>), dim3(nwg), dim3(kSmallThreads), 0, st, dprobs, dstart, nprob);
+      break;
+    case 32:
+      hipLaunchKernelGGL((k_assign_small<L, 32, FALLBACK>), dim3(nwg), dim3(kSmallThreads), 0, st, dprobs, dstart, nprob);
+      break;
+    default:
+      return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_assign_small(int low, int xd, bool fallback, const AssignProb* dprobs, const int32_t* dstart,
+                               int nprob, int nwg, hipStream_t st) {
+  if (low == kLowFP16)
+    return fallback ? launch_small_t<LowF16, true>(xd, dprobs, dstart, nprob, nwg, st)
+                    : launch_small_t<LowF16, false>(xd, dprobs, dstart, nprob, nwg, st);
+  if (low == kLowBF16)
+    return fallback ? launch_small_t<LowBF16, true>(xd, dprobs, dstart, nprob, nwg, st)
+                    : launch_small_t<LowBF16, false>(xd, dprobs, dstart, nprob, nwg, st);
   return hipErrorInvalidValue;
 }
 

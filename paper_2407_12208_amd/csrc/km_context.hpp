@@ -97,6 +97,8 @@ struct AssignPlan {
   int low;
   int DP;
   int k_pad;
+  int xd;           // > 0: the small-problem kernel with this row capacity
+  int gpw;          // its 32-point groups per wave
   int nwg;          // workgroups of the assignment kernel
   int nwg_pair;     // workgroups of the materialising kernel
   float alpha_f;    // alpha as applied (FP32)
@@ -104,6 +106,7 @@ struct AssignPlan {
   double alpha_used;
 };
 AssignPlan plan_assign(const km_precision& p, int64_t n, int d, int k);
+void set_small_sweep(AssignPlan& a, int64_t n, int64_t launch_points);
 size_t cq_elem_bytes(int low);
 
 // Launch helpers working on arrays of problems that share one AssignPlan

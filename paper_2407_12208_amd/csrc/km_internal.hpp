@@ -37,6 +37,14 @@ constexpr int pipe_points_per_wg(int low, int DP) { return kPipeWaves * 32 * mfm
 // points per workgroup of the assignment-mode kernel
 constexpr int assign_points_per_wg(int low, int DP) { return pipe_points_per_wg(low, DP); }
 constexpr int kDirectPointsPerWg = 64;
+// small-problem assignment kernel (d <= 32, k <= 64): four waves, each
+// sweeping `gpw` groups of 32 points
+constexpr int kSmallWaves = 4;
+constexpr int kSmallThreads = 64 * kSmallWaves;
+constexpr int kSmallMaxD = 32;
+constexpr int kSmallMaxK = 64;
+// register capacity of a point row in the small-problem kernel
+constexpr int small_xd(int d) { return d <= 8 ? 8 : d <= 16 ? 16 : d <= 32 ? 32 : 0; }
 
 // Accumulated per-problem results on the device.
 struct KResult {
@@ -77,6 +85,7 @@ struct AssignProb {
   int refine;           // 1: FP64 winner refinement, mindist and SSE partials;
                         // 0: labels and counters only (SSE left to the update)
   const int32_t* hint;  // nullable: an earlier assignment (seeds the search)
+  int gpw;              // small-problem kernel: 32-point groups per wave
 };
 
 struct ReduceProb {
@@ -111,12 +120,15 @@ struct UpdateProb {
   int* status;
   int64_t n;
   int d, k, ntiles;
+  int chunk;               // members per partial sum (upd_chunk(d))
 };
 
 hipError_t launch_prep(int low, const PrepProb* dprobs, const int32_t* dstart, int nprob, int nwg,
                        hipStream_t st);
 hipError_t launch_assign_mfma(int low, int DP, int mode, bool fallback, const AssignProb* dprobs,
                               const int32_t* dstart, int nprob, int nwg, hipStream_t st);
+hipError_t launch_assign_small(int low, int xd, bool fallback, const AssignProb* dprobs, const int32_t* dstart,
+                               int nprob, int nwg, hipStream_t st);
 hipError_t launch_assign_direct64(bool cmp64, int mode, const AssignProb* dprobs, const int32_t* dstart,
                                   int nprob, int nwg, hipStream_t st);
 hipError_t launch_reduce_parts(const ReduceProb* dprobs, int nprob, hipStream_t st);
@@ -125,7 +137,10 @@ hipError_t launch_quantize(int low, const float* in, int64_t count, uint16_t* ou
 
 // centre update (km_update.hip)
 constexpr int kUpdTile = 1024;   // points per histogram / scatter tile
-constexpr int kUpdChunk = 64;    // members per partial sum
+constexpr int kUpdChunk = 64;    // members per partial sum (the smallest; workspace bound)
+// Members per partial sum: rows of a few coordinates carry little work per
+// member, so a wave takes longer runs of them.
+constexpr int upd_chunk(int d) { return d <= 16 ? 8 * kUpdChunk : kUpdChunk; }
 hipError_t launch_update(const UpdateProb* dprobs, const UpdateProb* hprobs, int nprob,
                          const int32_t* dscratch_i32, hipStream_t st);
 

@@ -12,10 +12,11 @@
 //   3. scan_cl   per problem, cluster starts and chunk starts;
 //   4. scatter   stable counting sort of point indices by label: members of
 //                a cluster appear in ascending point order;
-//   5. chunksum  one wave per chunk of <= 64 consecutive members of one
-//                cluster: FP64 sums over fixed member groups, combined by a
-//                fixed butterfly;
-//   6. finalize  per cluster, sum of its chunk partials in order, division,
+//   5. chunksum  one wave per chunk of consecutive members of one cluster
+//                (64, or 512 when d <= 16): FP64 sums over fixed member
+//                groups, combined by a fixed butterfly;
+//   6. finalize  per cluster, sum of its chunk partials in a fixed
+//                lane-strided order with a fixed butterfly, division,
 //                one rounding to FP32, empty clusters keep their centre,
 //                squared move;
 //   7. shift     per problem, max_j ||c_j^new - c_j^old|| (FP64), and, when
@@ -112,7 +113,7 @@ k_upd_scan_cl(const UpdateProb* __restrict__ probs) {
   for (int base = 0; base < P.k; base += 1024) {
     const int j = base + tid;
     const int mj = j < P.k ? as_global(P.cstart)[j] : 0;
-    const int cj = (mj + kUpdChunk - 1) / kUpdChunk;
+    const int cj = (mj + P.chunk - 1) / P.chunk;
     a[tid] = mj;
     b[tid] = cj;
     __syncthreads();
@@ -201,7 +202,7 @@ k_upd_scatter(const UpdateProb* __restrict__ probs, const int32_t* __restrict__ 
   }
 }
 
-// 5. one wave per chunk of <= 64 members of one cluster.  Lanes are split
+// 5. one wave per chunk of members of one cluster (P.chunk at most).  Lanes are split
 // into G member groups x L lanes per member row; each lane sums its group's
 // members (every G-th member, ascending) in FP64 over its coordinates, then
 // the groups are combined by a fixed butterfly.  The order depends only on
@@ -342,15 +343,19 @@ k_upd_chunksum(const UpdateProb* __restrict__ probs, const int32_t* __restrict__
     if (as_global(P.chunk_start)[mid] <= c) lo = mid; else hi = mid - 1;
   }
   const int j = lo;
-  const int m0 = as_global(P.cstart)[j] + (c - as_global(P.chunk_start)[j]) * kUpdChunk;
-  const int m1 = (m0 + kUpdChunk) < as_global(P.cstart)[j + 1] ? (m0 + kUpdChunk) : as_global(P.cstart)[j + 1];
+  const int m0 = as_global(P.cstart)[j] + (c - as_global(P.chunk_start)[j]) * P.chunk;
+  const int m1 = (m0 + P.chunk) < as_global(P.cstart)[j + 1] ? (m0 + P.chunk) : as_global(P.cstart)[j + 1];
   if ((P.d & 3) == 0 && (((uintptr_t)P.X) & 15) == 0)
     chunk_rows<true>(P, c, j, m0, m1, lane);
   else
     chunk_rows<false>(P, c, j, m0, m1, lane);
 }
 
-// 6. per cluster: ordered sum of chunk partials, divide, round, keep empty
+// 6. per cluster: sum of its chunk partials, divide, round, keep empty.
+// Lanes are split into G chunk groups x L lanes per coordinate block (L the
+// coordinate count rounded up to a power of two, at most 64): group g sums
+// chunks c0+g, c0+g+G, ... in ascending order and the groups are combined by
+// a fixed butterfly, so the order depends only on the cluster's chunk count.
 __global__ void __launch_bounds__(256)
 k_upd_finalize(const UpdateProb* __restrict__ probs, const int32_t* __restrict__ wg_start, int nprob) {
   const int pi = find_prob(wg_start, nprob, blockIdx.x);
@@ -361,27 +366,33 @@ k_upd_finalize(const UpdateProb* __restrict__ probs, const int32_t* __restrict__
   const int mj = as_global(P.cstart)[j + 1] - as_global(P.cstart)[j];
   const int c0 = as_global(P.chunk_start)[j], c1 = as_global(P.chunk_start)[j + 1];
   const int d = P.d;
+  int L = 1;
+  while (L < d && L < 64) L <<= 1;
+  const int G = 64 / L;
+  const int g = lane / L, cl = lane % L;
   double mv2 = 0.0;
-  for (int l0 = 0; l0 < d; l0 += 64) {
-    const int l = l0 + lane;
-    if (l < d) {
+  for (int l0 = 0; l0 < d; l0 += L) {
+    const int l = l0 + cl;
+    double s = 0.0;
+    if (l < d && mj > 0) {
+#pragma unroll 4
+      for (int c = c0 + g; c < c1; c += G) s += as_global(P.chunk_sum)[(int64_t)c * d + l];
+    }
+    for (int o = L; o < 64; o <<= 1) s += __shfl_xor(s, o, kWave);
+    if (g == 0 && l < d) {
       const float old = as_global(P.C_old)[(int64_t)j * d + l];
-      float nv = old;
-      if (mj > 0) {
-        double s = 0.0;
-        for (int c = c0; c < c1; ++c) s += as_global(P.chunk_sum)[(int64_t)c * d + l];
-        nv = (float)(s / (double)mj);
-      }
+      const float nv = mj > 0 ? (float)(s / (double)mj) : old;
       as_global(P.C_new)[(int64_t)j * d + l] = nv;
       const double df = (double)nv - (double)old;
       mv2 += df * df;
     }
   }
   mv2 = wave_sum(mv2);
-  if (P.sse_out && lane == 0 && c1 > c0) {  // the cluster's SSE, its chunks in order
+  if (P.sse_out && c1 > c0) {  // the cluster's SSE: lane-strided chunks, fixed butterfly
     double e = 0.0;
-    for (int c = c0; c < c1; ++c) e += as_global(P.sse_chunk)[c];
-    as_global(P.sse_chunk)[c0] = e;
+    for (int c = c0 + lane; c < c1; c += 64) e += as_global(P.sse_chunk)[c];
+    e = wave_sum(e);
+    if (lane == 0) as_global(P.sse_chunk)[c0] = e;
   }
   if (lane == 0) {
     as_global(P.shift2)[j] = mv2;
@@ -434,7 +445,7 @@ hipError_t launch_update(const UpdateProb* dprobs, const UpdateProb* hprobs, int
     tiles += hprobs[i].ntiles;
     scatwg += (hprobs[i].ntiles + 3) / 4;
     clusters += hprobs[i].k;
-    chunkwg += (int)((hprobs[i].n + kUpdChunk - 1) / kUpdChunk + hprobs[i].k + 3) / 4;
+    chunkwg += (int)((hprobs[i].n + hprobs[i].chunk - 1) / hprobs[i].chunk + hprobs[i].k + 3) / 4;
     clwg += (hprobs[i].k + 3) / 4;
   }
   const int32_t* pre_tiles = dpre;
