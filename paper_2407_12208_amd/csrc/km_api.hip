@@ -465,7 +465,8 @@ static hipError_t enqueue_pass(km_context_impl* ctx, const AssignPlan& a, const 
                                bool refine, bool hint, hipStream_t st) {
   // every descriptor of the pass in one upload
   Pack pk;
-  const bool prep = uses_prep(a);
+  // the small-problem kernel prepares its centres itself
+  const bool prep = uses_prep(a) && !(mode == 0 && a.xd > 0);
   size_t o_pp = 0, o_ps = 0;
   int prep_wg = 0;
   if (prep) {
@@ -506,6 +507,7 @@ static hipError_t enqueue_pass(km_context_impl* ctx, const AssignPlan& a, const 
   ap.refine = refine ? 1 : 0;
   ap.hint = hint ? labels : nullptr;
   ap.gpw = a.gpw;
+  ap.alpha = a.alpha_f;
   const int nwg = mode == 0 ? a.nwg : a.nwg_pair;
   const int32_t apre[2] = {0, nwg};
   const size_t o_ap = pk.add(&ap, sizeof(ap));
@@ -720,7 +722,7 @@ hipError_t enqueue_batch_pass(km_context_impl* ctx, std::vector<BatchState*>& li
     std::vector<int> kp;
     int low = -1;
     for (BatchState* s : list) {
-      if (!uses_prep(s->plan)) continue;
+      if (!uses_prep(s->plan) || s->plan.xd > 0) continue;  // small kernel: prepared in the pass
       PrepProb q{};
       q.C = s->cur;
       q.Cq = s->bufs.Cq;
@@ -772,6 +774,7 @@ hipError_t enqueue_batch_pass(km_context_impl* ctx, std::vector<BatchState*>& li
       a.refine = final_pass ? 1 : 0;
       a.hint = s->it > 0 ? s->prob->labels : nullptr;  // the previous round's labels
       a.gpw = o.gpw;
+      a.alpha = o.alpha_f;
       ap.push_back(a);
       nw.push_back(o.nwg);
     }

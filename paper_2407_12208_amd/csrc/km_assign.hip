@@ -1078,10 +1078,12 @@ k_assign_pipe(const AssignProb* __restrict__ probs, const int32_t* __restrict__ 
 //
 // Same arithmetic and outputs as k_assign_pipe in assignment mode, for shapes
 // that are bound by memory and the vector epilogue rather than the matrix
-// cores (a few coordinates, a few dozen centres).  The centres' fragments
-// (at most two 32-centre blocks) stay in registers for the whole launch, their
-// accumulator starts and test constants in LDS, and each wave sweeps `gpw` groups of 32 points, loading
-// the rows of the next group before the epilogue of the current one.  Every
+// cores (a few coordinates, a few dozen centres).  Each workgroup rounds the
+// centres itself (no preparation launch); their fragments (at most two
+// 32-centre blocks) stay in registers for the whole launch, their
+// accumulator starts and test constants in LDS, and each wave sweeps `gpw`
+// groups of 32 points, loading the rows of the next group before the
+// epilogue of the current one.  Every
 // lane holds the full FP32 row of its point (the two lanes of a point hold
 // different centres of a block).  Flagged pairs can be frequent on such data
 // (a tenth of all pairs on normalised image features), so they are not
@@ -1175,26 +1177,48 @@ k_assign_small(const AssignProb* __restrict__ probs, const int32_t* __restrict__
   float xn[XD];
   load_rows(0, xn);
 
-  // FP32 centres (corrections, refinement) and test constants to LDS
+  // Centres, prepared by each workgroup itself (no separate launch): FP32
+  // rows to LDS (corrections, refinement), range and finiteness, then per
+  // centre the rounded row's squared norm nc in FP32 (coordinates in order),
+  // the accumulator start -nc/2 and the test constant alpha nc/2; rows past k
+  // start at -inf and never fail the test.
+  int bad = 0;
   for (int e = tid; e < kSmallMaxK * CS; e += kSmallThreads) {
     const int j = e / CS, l = e - j * CS;
-    s_c[e] = (j < k && l < d) ? as_global(P.C)[(int64_t)j * d + l] : 0.0f;
+    float v = 0.0f;
+    if (j < k && l < d) {
+      v = as_global(P.C)[(int64_t)j * d + l];
+      if (!__builtin_isfinite(v)) bad |= kStatusNonFinite;
+      if (L::kHasRange && __builtin_fabsf(v) >= L::kOverflow) bad |= kStatusRange;
+    }
+    s_c[e] = v;
   }
+  __syncthreads();
   if (tid < kSmallMaxK) {
-    s_ca[tid] = tid < P.k_pad ? as_global(P.ca)[tid] : 0.0f;
-    s_cinit[tid] = tid < P.k_pad ? as_global(P.cinit)[tid] : -__builtin_inff();
+    float nc = 0.0f;
+#pragma unroll
+    for (int l = 0; l < XD; ++l) {
+      if (l >= d) break;
+      const float f = L::tof(L::cvt(s_c[tid * CS + l]));
+      nc = __builtin_fmaf(f, f, nc);
+    }
+    const float hc = 0.5f * nc;
+    s_cinit[tid] = tid < k ? -hc : -__builtin_inff();
+    s_ca[tid] = tid < k ? P.alpha * hc : 0.0f;
   }
-
-  // centre fragments in registers (accumulator starts in LDS)
-  const KM_GLOBAL S* Cq = reinterpret_cast<const KM_GLOBAL S*>(as_global(P.Cq));
+  // centre fragments in registers: RNE of the LDS rows (zero past d and k)
   frag af[2][STEPS];
 #pragma unroll
   for (int b = 0; b < 2; ++b) {
 #pragma unroll
-    for (int s = 0; s < STEPS; ++s)
-      af[b][s] = b < kb ? *reinterpret_cast<const KM_GLOBAL frag*>(Cq + (int64_t)(b * 32 + (lane & 31)) * DP +
-                                                                 s * L::KS + hi * L::KV)
-                        : frag{};
+    for (int s = 0; s < STEPS; ++s) {
+#pragma unroll
+      for (int u = 0; u < L::KV; ++u) {
+        const int l = s * L::KS + hi * L::KV + u;
+        const float v = (b < kb && l < XD) ? s_c[(b * 32 + (lane & 31)) * CS + (l < XD ? l : 0)] : 0.0f;
+        af[b][s][u] = L::cvt(v);
+      }
+    }
   }
   // accumulator start of block b: -nc_j/2 of the lane's rows
   auto acc_start = [&](int b) {
@@ -1225,7 +1249,6 @@ k_assign_small(const AssignProb* __restrict__ probs, const int32_t* __restrict__
     cam[b] = m;
   }
 
-  int bad = 0;
   double sse = 0.0;
   unsigned long long ncorr = 0;
   for (int q = 0; q < gpw; ++q) {

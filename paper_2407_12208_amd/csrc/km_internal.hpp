@@ -86,6 +86,7 @@ struct AssignProb {
                         // 0: labels and counters only (SSE left to the update)
   const int32_t* hint;  // nullable: an earlier assignment (seeds the search)
   int gpw;              // small-problem kernel: 32-point groups per wave
+  float alpha;          // small-problem kernel: alpha (FP32), for its own centre constants
 };
 
 struct ReduceProb {

@@ -132,3 +132,21 @@ def test_small_repeatable_and_outputs_optional(ctx):
     assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1]) and a[2] == b[2]
     lab, _, _, _ = km.kmeans_assign(ctx, Xd, Cd, prec(), stats=False)
     assert np.array_equal(host(lab), a[0])
+
+
+def test_small_centre_errors(ctx):
+    # the small-problem kernel checks the centres itself (no preparation
+    # launch): a non-finite centre and an FP16-overflowing one are reported
+    X = np.ones((300, 5), dtype=np.float32)
+    C = np.ones((4, 5), dtype=np.float32)
+    Cn = C.copy()
+    Cn[2, 3] = np.inf
+    with pytest.raises(km.KMeansError) as e:
+        km.kmeans_assign(ctx, dev(X), dev(Cn), prec())
+    assert e.value.code == -3
+    Cr = C.copy()
+    Cr[1, 0] = -7.0e4
+    with pytest.raises(km.KMeansError) as e:
+        km.kmeans_assign(ctx, dev(X), dev(Cr), prec())
+    assert e.value.code == -2
+    km.kmeans_assign(ctx, dev(X), dev(Cr), prec(km.KM_LOW_BF16))
