@@ -14,8 +14,8 @@ resident in HBM before timing starts.
 Prints ONE JSON line.  Extra keys report the assignment kernel alone, the
 plain FP64 direct-formula kernel on the same input, the fallback ratio, the
 single-solve Lloyd rate (20,000 x 32, k = 16), the large clustering
-(2,000,000 x 64, 1,024 blobs, 50 rounds) in BF16/FP16 -> FP64, uniform FP32
-and plain FP64, the batched segmentation-shaped instances (256 problems, one
+(2,000,000 x 64, 1,024 blobs, 50 rounds) in BF16/FP16 -> FP64 (BF16 also
+with the hardware-aware threshold), uniform FP32 and plain FP64, the batched segmentation-shaped instances (256 problems, one
 batched solve against one solve per problem), serving, and, as
 `cpu_baseline`, the CPU oracle timed on a bounded sample of the same
 workload.
@@ -149,6 +149,7 @@ def large_bench(km, ctx, torch, W, np):
     iters = cfg["iters"]
     out = {"n": cfg["n"], "d": cfg["d"], "k": cfg["k"], "rounds": iters}
     variants = (("bf16_fp64", km.Precision(km.KM_LOW_BF16)),
+                ("bf16_fp64_hw_alpha", km.Precision(km.KM_LOW_BF16, km.KM_ALPHA_HW)),
                 ("fp16_fp64", km.Precision(km.KM_LOW_FP16)),
                 ("fp32_uniform", km.Precision(km.KM_LOW_FP32, km.KM_ALPHA_NONE)),
                 ("fp64_direct", km.Precision(km.KM_EXACT64)))
@@ -168,6 +169,8 @@ def large_bench(km, ctx, torch, W, np):
                                                          out[name]["eta"]))
     out["speedup_fp16_fp64_vs_fp64_direct"] = (out["fp16_fp64"]["rounds_per_s"] /
                                                out["fp64_direct"]["rounds_per_s"])
+    out["speedup_bf16_hw_alpha_vs_fp64_direct"] = (out["bf16_fp64_hw_alpha"]["rounds_per_s"] /
+                                                   out["fp64_direct"]["rounds_per_s"])
     return out
 
 
@@ -230,6 +233,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-extra", action="store_true", help="skip the extra measurements")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--no-large", action="store_true",
+                    help="skip the large-clustering measurement")
     ap.add_argument("--batch-problems", type=int, default=256,
                     help="problems in the batched measurement (0 = skip)")
     ap.add_argument("--serve-requests", type=int, default=48,
@@ -360,7 +365,8 @@ def main():
             res[name] = cs["iters"] / dt
         extra["lloyd_small_iters_per_s"] = res["mixed_fp16_fp64"]
         extra["lloyd_small_iters_per_s_fp64_direct"] = res["fp64_direct"]
-        extra["large_clustering"] = large_bench(km, ctx, torch, W, np)
+        if not args.no_large:
+            extra["large_clustering"] = large_bench(km, ctx, torch, W, np)
         if args.batch_problems > 0:
             extra["batched_segmentation"] = batch_bench(km, ctx, torch, W, np,
                                                         count=args.batch_problems)

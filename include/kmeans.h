@@ -74,8 +74,19 @@ enum {
                              test eq:quantis-reliability-test (default)      */
   KM_ALPHA_PAPER_ALG = 1, /* alpha = rho gamma: the listing alg:mp-dist      */
   KM_ALPHA_EXPLICIT = 2,  /* alpha = km_precision.alpha (>= 0)               */
-  KM_ALPHA_NONE = 3       /* no fallback: uniform low-precision expanded
+  KM_ALPHA_NONE = 3,      /* no fallback: uniform low-precision expanded
                              formula (the paper's "FP16"/"BF16"/"FP32" rows) */
+  KM_ALPHA_HW = 4         /* alpha = rho [2 gamma_{d+2}(2^-23)
+                                          + 2 (2u_l + u_l^2)(1 + u_l)^2]:
+                             the error decomposition of Section 4.3
+                             (arithmetic error of the expanded formula plus
+                             the conversion error of the quantised inputs)
+                             with the cross term accumulated in FP32 by the
+                             matrix cores, whose products of FP16/BF16
+                             operands are exact.  Kept pairs then have
+                             relative error <= 1/(rho-1) against the exact
+                             distance of the FP32 inputs.  A variant for this
+                             hardware, not the paper's rule; rho > 2.      */
 };
 /* If (d+2) u_l >= 1 gamma is undefined and every pair is corrected. */
 

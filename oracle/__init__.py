@@ -231,8 +231,23 @@ def alpha_value(fmt: int, d: int, rho: float = 5.0, form: str = "eq") -> float:
 
     ``form="eq"``: alpha = rho * 2 gamma^l_{d+2} (E^l of Section 4.3 with the
     test eq:quantis-reliability-test); ``form="alg"``: alpha = rho *
-    gamma^l_{d+2} (the listing of alg:mp-dist).  inf when gamma is undefined.
+    gamma^l_{d+2} (the listing of alg:mp-dist); ``form="hw"``: the same
+    decomposition with FP32 accumulation of exact products (a variant, not
+    the paper's rule).  inf when gamma is undefined.
     """
+    if form == "hw":
+        # Section 4.3's two error sources re-derived for a cross term whose
+        # products are exact and whose sum is accumulated in FP32:
+        #   |q^ - d(x~,c~)^2| <= gamma^{32}_{d+2} (||x~||^2 + 2|x~|^T|c~| + ||c~||^2)
+        #                     <= 2 gamma^{32}_{d+2} S,
+        #   conversion error C <= 2(2u_l + u_l^2) (||x||^2 + ||c||^2)
+        #                     <= 2(2u_l + u_l^2)(1 + u_l)^2 S,
+        # with S = ||x~||^2 + ||c~||^2; the FP32 unit is taken as 2^-23.
+        g32 = gamma(d + 2, 2.0 ** -23)
+        if not np.isfinite(g32):
+            return float("inf")
+        ul = unit_roundoff(fmt)
+        return rho * (2.0 * g32 + 2.0 * (2.0 * ul + ul * ul) * (1.0 + ul) ** 2)
     g = gamma(d + 2, unit_roundoff(fmt))
     if not np.isfinite(g):
         return float("inf")

@@ -16,7 +16,7 @@ from dataclasses import dataclass
 
 __all__ = [
     "KM_LOW_FP16", "KM_LOW_BF16", "KM_LOW_FP32", "KM_EXACT64",
-    "KM_ALPHA_PAPER_EQ", "KM_ALPHA_PAPER_ALG", "KM_ALPHA_EXPLICIT", "KM_ALPHA_NONE",
+    "KM_ALPHA_PAPER_EQ", "KM_ALPHA_PAPER_ALG", "KM_ALPHA_EXPLICIT", "KM_ALPHA_NONE", "KM_ALPHA_HW",
     "KM_SYNC", "KMeansError", "Precision", "Stats", "Problem", "library_path", "lib",
     "Context", "kmeans_context_create", "kmeans_assign", "kmeans_update",
     "kmeans_lloyd", "kmeans_solve_batch", "kmeans_pairwise", "kmeans_quantize",
@@ -26,7 +26,7 @@ __all__ = [
 ]
 
 KM_LOW_FP16, KM_LOW_BF16, KM_LOW_FP32, KM_EXACT64 = 0, 1, 2, 3
-KM_ALPHA_PAPER_EQ, KM_ALPHA_PAPER_ALG, KM_ALPHA_EXPLICIT, KM_ALPHA_NONE = 0, 1, 2, 3
+KM_ALPHA_PAPER_EQ, KM_ALPHA_PAPER_ALG, KM_ALPHA_EXPLICIT, KM_ALPHA_NONE, KM_ALPHA_HW = 0, 1, 2, 3, 4
 KM_SYNC = 1
 KM_LABELS_HINT = 2
 KM_OK, KM_PENDING = 0, 1

@@ -78,8 +78,9 @@ km_precision precision_or_default(const km_precision* p) {
 int32_t validate_precision(const km_precision& p) {
   if (p.low < KM_LOW_FP16 || p.low > KM_EXACT64) return KM_ERR_ARG;
   if (p.low == KM_EXACT64) return KM_OK;
-  if (p.alpha_mode < KM_ALPHA_PAPER_EQ || p.alpha_mode > KM_ALPHA_NONE) return KM_ERR_ARG;
-  if ((p.alpha_mode == KM_ALPHA_PAPER_EQ || p.alpha_mode == KM_ALPHA_PAPER_ALG) && !(p.rho > 2.0))
+  if (p.alpha_mode < KM_ALPHA_PAPER_EQ || p.alpha_mode > KM_ALPHA_HW) return KM_ERR_ARG;
+  if ((p.alpha_mode == KM_ALPHA_PAPER_EQ || p.alpha_mode == KM_ALPHA_PAPER_ALG ||
+       p.alpha_mode == KM_ALPHA_HW) && !(p.rho > 2.0))
     return KM_ERR_ARG;  // the relative bound needs rho~ > 2 (Section 4.3)
   if (p.alpha_mode == KM_ALPHA_EXPLICIT && !(p.alpha >= 0.0)) return KM_ERR_ARG;
   return KM_OK;
@@ -88,6 +89,17 @@ int32_t validate_precision(const km_precision& p) {
 double alpha_for(const km_precision& p, int d) {
   if (p.low == KM_EXACT64 || p.alpha_mode == KM_ALPHA_NONE) return -1.0;
   if (p.alpha_mode == KM_ALPHA_EXPLICIT) return p.alpha;
+  if (p.alpha_mode == KM_ALPHA_HW) {
+    // arithmetic error of the expanded formula with FP32 accumulation
+    // (rounding unit taken as 2^-23, room for any accumulator rounding)
+    // plus the conversion error of the rounded inputs
+    const double u32 = ldexp(1.0, -23);
+    const double m32 = (double)(d + 2) * u32;
+    if (!(m32 < 1.0)) return INFINITY;
+    const double ul = unit_roundoff_low(p.low);
+    const double conv = 2.0 * (2.0 * ul + ul * ul) * (1.0 + ul) * (1.0 + ul);
+    return p.rho * (2.0 * m32 / (1.0 - m32) + conv);
+  }
   const double mu = (double)(d + 2) * unit_roundoff_low(p.low);
   if (!(mu < 1.0)) return INFINITY;  // gamma undefined: correct every pair
   const double g = mu / (1.0 - mu);

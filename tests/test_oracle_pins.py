@@ -400,3 +400,88 @@ def test_label_gate_logic():
     B = np.full_like(dist, 0.1)
     gated = oracle.label_gate(dist, B, np.array([0, 0]))
     assert gated.tolist() == [True, False]
+
+
+def _fp32_expanded(X, C, fmt):
+    """Expanded formula of the rounded inputs evaluated in float32 (numpy's
+    summation order; the products of FP16/BF16 values are exact in FP32)."""
+    Xq = oracle.round_low(X, fmt).astype(np.float32)
+    Cq = oracle.round_low(C, fmt).astype(np.float32)
+    nx = (Xq * Xq).sum(axis=1, dtype=np.float32)
+    nc = (Cq * Cq).sum(axis=1, dtype=np.float32)
+    G = (Xq @ Cq.T).astype(np.float32)
+    dh = np.maximum(nx[:, None] + nc[None, :] - np.float32(2) * G, np.float32(0))
+    S = nx[:, None].astype(np.float64) + nc[None, :].astype(np.float64)
+    return dh.astype(np.float64), S
+
+
+def _boundary_pairs(d, seed):
+    # points at log-uniform distances 1e-4..10 from centres in [-10, 10]^d:
+    # the test's threshold falls inside the range, on both sides
+    g = np.random.default_rng(seed)
+    C = g.uniform(-10, 10, size=(24, d)).astype(np.float32)
+    owner = g.integers(0, 24, size=600)
+    delta = 10.0 ** g.uniform(-4, 1, size=(600, 1))
+    z = g.standard_normal((600, d))
+    X = (C[owner].astype(np.float64) + delta * z / np.sqrt(d)).astype(np.float32)
+    return X, C
+
+
+def _aligned_pairs(d, fmt, seed):
+    # coordinates in [8, 16): c rounds down by ~ulp/2, x = c + (j + 0.1) ulp
+    # rounds up by ~ulp/2, so the rounded difference is (j + 1) ulp in every
+    # coordinate: the quantisation error has the sign of the difference
+    g = np.random.default_rng(seed)
+    ulp = 16.0 * oracle.unit_roundoff(fmt)  # spacing of the format in [8, 16)
+    rows_x, rows_c = [], []
+    for j in range(1, 41):
+        m = g.integers(0, int(4 / ulp), size=d)
+        c = 8.0 + (m + 0.45) * ulp
+        x = 8.0 + (m + j + 0.55) * ulp
+        rows_x.append(x)
+        rows_c.append(c)
+    return np.array(rows_x, dtype=np.float32), np.array(rows_c, dtype=np.float32)
+
+
+@pytest.mark.parametrize("fmt", [oracle.FP16, oracle.BF16])
+@pytest.mark.parametrize("d", [5, 64, 128])
+def test_hw_alpha_kept_pairs_obey_relative_bound(fmt, d):
+    # Section 4.3's decomposition (arithmetic error of the expanded formula
+    # plus the conversion error of the rounded inputs) with FP32 accumulation:
+    # a pair whose FP32 expanded value passes d^ > alpha_hw * S is within
+    # 1/(rho - 1) of the exact distance of the FP32 inputs
+    rho = 5.0
+    a = oracle.alpha_value(fmt, d, rho, "hw")
+    a_bad = rho * 2.0 * oracle.gamma(d + 2, 2.0 ** -23)  # conversion term dropped
+    X, C = _boundary_pairs(d, 40 + d + fmt)
+    dh, S = _fp32_expanded(X, C, fmt)
+    exact = oracle.dist_rows(X, C)
+    kept = dh > a * S
+    assert 0.05 < kept.mean() < 0.999  # both sides of the threshold are present
+    rel = np.abs(dh - exact)[kept] / exact[kept]
+    assert np.all(rel <= (1.0 / (rho - 1.0)) * (1 + 1e-6))
+    # the paper's alpha (FP16/BF16 arithmetic throughout) is larger
+    assert a < oracle.alpha_value(fmt, d, rho, "eq")
+    # quantisation errors aligned with the differences (paired rows)
+    Xa, Ca = _aligned_pairs(d, fmt, 50 + d + fmt)
+    dha, Sa = _fp32_expanded(Xa, Ca, fmt)
+    dha, Sa = np.diag(dha), np.diag(Sa)
+    exa = np.diag(oracle.dist_rows(Xa, Ca))
+    rela = np.abs(dha - exa) / exa
+    keep_a = dha > a * Sa
+    assert np.all(rela[keep_a] <= (1.0 / (rho - 1.0)) * (1 + 1e-6))
+    # a planted mistake: without the conversion term the threshold keeps
+    # aligned pairs whose quantisation error exceeds the bound (where the
+    # FP32 arithmetic term alone is small enough for this to happen)
+    if fmt == oracle.BF16 or d <= 8:
+        assert np.any(rela[dha > a_bad * Sa] > 1.0 / (rho - 1.0))
+
+
+def test_hw_alpha_cancellation_all_flagged():
+    # every coordinate near 1e3 with spread 1e-2: the conversion error alone
+    # exceeds the distances, so the hardware-aware test flags every pair
+    X, C = W.cancellation_pair(200, 16, 64, seed=41)
+    for fmt in (oracle.FP16, oracle.BF16):
+        dh, S = _fp32_expanded(X, C, fmt)
+        a = oracle.alpha_value(fmt, 64, 5.0, "hw")
+        assert np.all(dh <= a * S)
