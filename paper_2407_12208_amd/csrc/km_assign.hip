@@ -1126,16 +1126,16 @@ __global__ void __launch_bounds__(kSmallThreads, XD == 8 ? 4 : XD == 16 ? 3 : 2)
 k_assign_small(const AssignProb* __restrict__ probs, const int32_t* __restrict__ wg_start, int nprob) {
   constexpr int DP = XD < 16 ? 16 : XD;  // row extent of the quantised centres
   constexpr int STEPS = DP / L::KS;
-  constexpr int CS = XD + 1;             // LDS row stride of the FP32 centres
+  constexpr int CS = XD + 4;             // LDS row stride of FP32 rows (16-byte aligned)
   using S = typename L::S;
   using frag = typename L::frag;
-  __shared__ float s_ca[kSmallMaxK];
+  __shared__ __attribute__((aligned(16))) float s_ca[kSmallMaxK];
   __shared__ __attribute__((aligned(16))) float s_cinit[kSmallMaxK];
-  __shared__ float s_c[kSmallMaxK * CS];
+  __shared__ __attribute__((aligned(16))) float s_c[kSmallMaxK * CS];
   // correction queue of a 32-centre block (at most 32 x 32 pairs), the
   // group's point rows and each point's best corrected pair
   __shared__ int s_q[FALLBACK ? kSmallWaves : 1][FALLBACK ? 32 * 32 : 1];
-  __shared__ float s_x[FALLBACK ? kSmallWaves : 1][FALLBACK ? 32 * CS : 1];
+  __shared__ __attribute__((aligned(16))) float s_x[FALLBACK ? kSmallWaves : 1][FALLBACK ? 32 * CS : 4];
   __shared__ unsigned long long s_key[FALLBACK ? kSmallWaves : 1][32];
   __shared__ double s_sse[kSmallWaves];
   __shared__ unsigned long long s_corr[kSmallWaves];
@@ -1309,19 +1309,25 @@ k_assign_small(const AssignProb* __restrict__ probs, const int32_t* __restrict__
         if (__ballot(m[b] + cam[b] >= hx) != 0) {
           uint32_t fm = 0;
 #pragma unroll
-          for (int r = 0; r < 16; ++r) {
-            const bool f = acc[b][r] + s_ca[b * 32 + acc_row(r, lane)] >= hx;
-            fm |= (uint32_t)f << r;
-            acc[b][r] = f ? -__builtin_inff() : acc[b][r];
+          for (int q = 0; q < 4; ++q) {  // rows 8q + 4hi + 0..3 of the block
+            const f32x4 ca4 = *reinterpret_cast<const f32x4*>(&s_ca[b * 32 + 8 * q + 4 * hi]);
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+              const int r = 4 * q + e;
+              const bool f = acc[b][r] + ca4[e] >= hx;
+              fm |= (uint32_t)f << r;
+              acc[b][r] = f ? -__builtin_inff() : acc[b][r];
+            }
           }
           m[b] = max16(acc[b]);
           fm &= vmask[b];
           if (!staged) {  // the group's rows and best corrected pairs
             staged = true;
-            if (hi == 0) {
+            if (hi == 0) {  // whole rows: the coordinates past d are zero
 #pragma unroll
-              for (int l = 0; l < XD; ++l)
-                if (l < d) s_x[wave][(lane & 31) * CS + l] = x[l];
+              for (int l = 0; l < XD; l += 4)
+                *reinterpret_cast<f32x4*>(&s_x[wave][(lane & 31) * CS + l]) =
+                    f32x4{x[l], x[l + 1], x[l + 2], x[l + 3]};
               s_key[wave][lane & 31] = ~0ull;
             }
           }
@@ -1348,12 +1354,19 @@ k_assign_small(const AssignProb* __restrict__ probs, const int32_t* __restrict__
             const int pt = code & 31, j = code >> 5;
             const float* xr = &s_x[wave][pt * CS];
             const float* cr = &s_c[j * CS];
+            // four coordinates per LDS access; both rows are zero past d,
+            // and a zero term leaves the FP64 sum unchanged
             double sq = 0.0;
 #pragma unroll
-            for (int l = 0; l < XD; ++l) {
-              if (l >= d) break;
-              const double t = (double)xr[l] - (double)cr[l];
-              sq = __builtin_fma(t, t, sq);
+            for (int l0 = 0; l0 < XD; l0 += 4) {
+              if (l0 >= d) break;
+              const f32x4 a4 = *reinterpret_cast<const f32x4*>(xr + l0);
+              const f32x4 c4 = *reinterpret_cast<const f32x4*>(cr + l0);
+#pragma unroll
+              for (int e = 0; e < 4; ++e) {
+                const double t = (double)a4[e] - (double)c4[e];
+                sq = __builtin_fma(t, t, sq);
+              }
             }
             // smallest value, then lowest index: FP32 bits of a
             // non-negative value order like the value
