@@ -162,6 +162,8 @@ AssignPlan plan_assign(const km_precision& p, int64_t n, int d, int k) {
       set_small_sweep(a, n, n);
     }
   }
+  a.gpw_own = a.gpw;
+  a.nwg_own = a.nwg;
   return a;
 }
 
@@ -447,11 +449,12 @@ int32_t check_shape(int64_t n, int32_t d, int32_t k, const km_precision& p) {
 }
 
 void plan_pass(Plan& pl, const AssignPlan& a) {
+  const int parts = std::max(std::max(a.nwg, a.nwg_own), a.nwg_pair);
   pl.add<char>((size_t)a.k_pad * a.DP * 4);
   pl.add<float>(a.k_pad);
   pl.add<float>(a.k_pad);
-  pl.add<double>(std::max(a.nwg, a.nwg_pair));
-  pl.add<unsigned long long>(std::max(a.nwg, a.nwg_pair));
+  pl.add<double>(parts);
+  pl.add<unsigned long long>(parts);
   pl.add<int>(1);
   pl.add<KResult>(1);
 }
@@ -461,8 +464,9 @@ PassBufs carve_pass(Arena& ar, const AssignPlan& a) {
   b.Cq = ar.take<char>((size_t)a.k_pad * a.DP * 4);
   b.cinit = ar.take<float>(a.k_pad);
   b.ca = ar.take<float>(a.k_pad);
-  b.sse_part = ar.take<double>(std::max(a.nwg, a.nwg_pair));
-  b.corr_part = ar.take<unsigned long long>(std::max(a.nwg, a.nwg_pair));
+  const int parts = std::max(std::max(a.nwg, a.nwg_own), a.nwg_pair);
+  b.sse_part = ar.take<double>(parts);
+  b.corr_part = ar.take<unsigned long long>(parts);
   b.status = ar.take<int>(1);
   b.result = ar.take<KResult>(1);
   return b;
@@ -765,6 +769,10 @@ hipError_t enqueue_batch_pass(km_context_impl* ctx, std::vector<BatchState*>& li
     for (size_t j = i; j < list.size(); ++j) {
       const AssignPlan& o = list[j]->plan;
       if (taken[j] || o.route != sh.route || o.DP != sh.DP || o.low != sh.low || o.xd != sh.xd) continue;
+      // the final pass refines and sums the SSE per workgroup: the problem's
+      // own partition, as when it runs alone
+      const int gpw = final_pass ? o.gpw_own : o.gpw;
+      const int nwg = final_pass ? o.nwg_own : o.nwg;
       taken[j] = true;
       BatchState* s = list[j];
       AssignProb a{};
@@ -785,10 +793,10 @@ hipError_t enqueue_batch_pass(km_context_impl* ctx, std::vector<BatchState*>& li
       a.oma = o.oma;
       a.refine = final_pass ? 1 : 0;
       a.hint = s->it > 0 ? s->prob->labels : nullptr;  // the previous round's labels
-      a.gpw = o.gpw;
+      a.gpw = gpw;
       a.alpha = o.alpha_f;
       ap.push_back(a);
-      nw.push_back(o.nwg);
+      nw.push_back(nwg);
     }
     hipError_t e = run_assign(ctx, sh, 0, ap, nw, st);
     if (e != hipSuccess) return e;
@@ -803,7 +811,7 @@ hipError_t enqueue_batch_pass(km_context_impl* ctx, std::vector<BatchState*>& li
     r.sse_out = (final_pass && s->prob->sse_hist) ? s->prob->sse_hist + s->it : nullptr;
     r.result = s->bufs.result;
     r.pairs = s->prob->n * (long long)s->prob->k;
-    r.nparts = s->plan.nwg;
+    r.nparts = final_pass ? s->plan.nwg_own : s->plan.nwg;
     rp.push_back(r);
   }
   return run_reduce(ctx, rp, st);

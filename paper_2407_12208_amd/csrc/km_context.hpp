@@ -98,7 +98,10 @@ struct AssignPlan {
   int DP;
   int k_pad;
   int xd;           // > 0: the small-problem kernel with this row capacity
-  int gpw;          // its 32-point groups per wave
+  int gpw;          // its 32-point groups per wave (may follow a batched launch)
+  int gpw_own;      // groups per wave from the problem alone: passes whose
+  int nwg_own;      // SSE comes from per-workgroup partials use these, so the
+                    // partition (and the FP64 sum) never depends on the batch
   int nwg;          // workgroups of the assignment kernel
   int nwg_pair;     // workgroups of the materialising kernel
   float alpha_f;    // alpha as applied (FP32)

@@ -274,3 +274,25 @@ def test_batch_segmentation_vs_oracle(ctx):
         assert host(it.sse_hist)[0] == pytest.approx(ref["sse_hist"][0], rel=1e-6)
         check_assignment(b["X"], host(it.C), 0, st["alpha_used"], host(it.labels), None,
                          None, None, min_coverage=0.9)
+
+
+def test_batch_equals_alone_when_the_launch_sweeps_longer(ctx):
+    # four 300,000-point problems (d = 5, k = 40): alone each sweeps one group
+    # of points per wave, the batched launch (1.2 M points) two; labels,
+    # centres, distances and every SSE are still identical bit for bit
+    inst = []
+    for i in range(4):
+        X, _, _ = W.blobs(300_000, 5, 40, seed=700 + i, std=0.3)
+        inst.append((X, W.init_centroids(X, 40, 710 + i)))
+    T = 4
+    items = [km.BatchItem(X=dev(X), C=dev(C0), max_iter=T) for X, C0 in inst]
+    stats = km.kmeans_solve_batch(ctx, items, FP16, with_mindist=True)
+    for i, (X, C0) in enumerate(inst):
+        Cd = dev(C0)
+        _, lab, mind, sse_hist, st = km.kmeans_lloyd(ctx, dev(X), Cd, T, prec=FP16,
+                                                     mindist=True, sse_hist=True)
+        np.testing.assert_array_equal(host(items[i].C), host(Cd))
+        np.testing.assert_array_equal(host(items[i].labels), host(lab))
+        np.testing.assert_array_equal(host(items[i].mindist), host(mind))
+        np.testing.assert_array_equal(host(items[i].sse_hist), host(sse_hist))
+        assert stats[i]["n_corrected"] == st["n_corrected"]
