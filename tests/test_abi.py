@@ -51,11 +51,16 @@ def test_host_only_helpers():
     import oracle
     for fmt, low in ((0, km.KM_LOW_FP16), (1, km.KM_LOW_BF16)):
         for d in (5, 32, 128):
-            a = km.kmeans_alpha(km.Precision(low, km.KM_ALPHA_PAPER_EQ, 5.0), d)
-            ref = oracle.alpha_value(fmt, d, 5.0, "eq")
-            assert a == pytest.approx(ref, rel=1e-7)
+            for mode, form in ((km.KM_ALPHA_PAPER_EQ, "eq"), (km.KM_ALPHA_PAPER_ALG, "alg"),
+                               (km.KM_ALPHA_HW, "hw")):
+                a = km.kmeans_alpha(km.Precision(low, mode, 5.0), d)
+                ref = oracle.alpha_value(fmt, d, 5.0, form)
+                assert a == pytest.approx(ref, rel=1e-7), (fmt, d, form)
+    for mode in (km.KM_ALPHA_PAPER_EQ, km.KM_ALPHA_HW):
+        with pytest.raises(km.KMeansError):
+            km.kmeans_alpha(km.Precision(km.KM_LOW_FP16, mode, 2.0), 8)
     with pytest.raises(km.KMeansError):
-        km.kmeans_alpha(km.Precision(km.KM_LOW_FP16, km.KM_ALPHA_PAPER_EQ, 2.0), 8)
+        km.kmeans_alpha(km.Precision(km.KM_LOW_FP16, km.KM_ALPHA_HW + 1, 5.0), 8)
     # context creation without a GPU fails cleanly with a device error
     import torch
     if not torch.cuda.is_available():
