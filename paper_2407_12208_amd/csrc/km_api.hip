@@ -5,6 +5,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <climits>
 #include <new>
 #include <map>
 #include <vector>
@@ -893,12 +894,81 @@ extern "C" int32_t kmeans_solve_batch(km_context* ctx, km_problem* probs, int32_
   (void)results;
   bool need_tol = false;
   for (int i = 0; i < count; ++i) need_tol |= probs[i].tol > 0.0;
+  // Sweep-length tuner of the small-problem launches: the first rounds run
+  // with 2, 4 and 8 groups per wave (timed with events around the
+  // assignment launches) and the fastest is kept for the rest.  These are
+  // real rounds: labels and counts do not depend on the partition and the
+  // rounds' SSE comes from the update, so results are the same whatever is
+  // chosen (the final pass uses each problem's own partition).
+  static const int kTuneGpw[3] = {2, 4, 8};
+  bool tune = false;
+  {
+    // every problem active through the tuning rounds, so that each round
+    // times the same launches
+    int64_t small_pts = 0;
+    int min_iter = INT32_MAX;
+    for (auto& s : S) {
+      if (s.plan.xd > 0) small_pts += s.prob->n;
+      min_iter = std::min(min_iter, (int)s.prob->max_iter);
+    }
+    tune = !ctx->timing && !need_tol && small_pts >= 2 * (int64_t)kSmallWaves * 32 * 4096 && min_iter >= 4;
+  }
+  auto apply_gpw = [&](int g) {
+    for (auto& s : S)
+      if (s.plan.xd > 0) {
+        s.plan.gpw = std::max(g, s.plan.gpw_own);
+        const int64_t ppw = (int64_t)kSmallWaves * 32 * s.plan.gpw;
+        s.plan.nwg = (int)((s.prob->n + ppw - 1) / ppw);
+      }
+  };
+  int round = 0;
+  int ev_mark[4] = {0, 0, 0, 0};
+  // the tuner borrows the context's launch timing; it is off again however
+  // this call returns
+  struct TimingOff {
+    km_context_impl* c;
+    bool on;
+    ~TimingOff() {
+      if (on) {
+        c->timing = false;
+        c->ev_used = 0;
+      }
+    }
+  } timing_off{ctx, tune};
+  if (tune) {
+    ctx->timing = true;
+    ctx->ev_used = 0;
+  }
   for (;;) {
     std::vector<BatchState*> act;
     for (auto& s : S)
       if (!s.done) act.push_back(&s);
     if (act.empty()) break;
+    if (tune && round < 3) apply_gpw(kTuneGpw[round]);
     KM_HIP(enqueue_batch_round(ctx, act, st));
+    if (tune && round < 3) ev_mark[round + 1] = ctx->ev_used;
+    if (tune && round == 2) {
+      KM_HIP(hipEventSynchronize(ctx->timing_event(2 * ev_mark[3] - 1)));
+      int best = 0;
+      float best_ms = 0.0f;
+      for (int r = 0; r < 3; ++r) {
+        float tot = 0.0f;
+        for (int e = ev_mark[r]; e < ev_mark[r + 1]; ++e) {
+          float ms = 0.0f;
+          KM_HIP(hipEventElapsedTime(&ms, ctx->timing_event(2 * e), ctx->timing_event(2 * e + 1)));
+          tot += ms;
+        }
+        if (r == 0 || tot < best_ms) {
+          best = r;
+          best_ms = tot;
+        }
+      }
+      apply_gpw(kTuneGpw[best]);
+      ctx->timing = false;
+      ctx->ev_used = 0;
+      tune = false;
+    }
+    ++round;
     if (need_tol) {
       for (size_t i = 0; i < act.size(); ++i)
         KM_HIP(hipMemcpyAsync(ctx->h_result + i, act[i]->bufs.result, sizeof(KResult), hipMemcpyDeviceToHost, st));
