@@ -32,6 +32,7 @@ def host(t):
 FP16 = km.Precision(km.KM_LOW_FP16, km.KM_ALPHA_PAPER_EQ, 5.0)
 BF16 = km.Precision(km.KM_LOW_BF16, km.KM_ALPHA_PAPER_EQ, 5.0)
 FP64 = km.Precision(km.KM_EXACT64)
+BF16_HW = km.Precision(km.KM_LOW_BF16, km.KM_ALPHA_HW, 5.0)
 
 
 def assert_within_ulps(a, b, ulps=1):
@@ -245,7 +246,7 @@ def _instances():
     return out
 
 
-@pytest.mark.parametrize("prec", [FP16, BF16, FP64])
+@pytest.mark.parametrize("prec", [FP16, BF16, FP64, BF16_HW])
 def test_batch_equals_alone(ctx, prec):
     inst = _instances()
     T = 6

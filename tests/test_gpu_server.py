@@ -57,20 +57,22 @@ def _check_against_lloyd(ctx, r, X, C0, iters):
     assert r["sse_hist"][0] == pytest.approx(sse0, rel=1e-6)
 
 
-def test_alone_equals_in_mix(ctx):
+@pytest.mark.parametrize("prec", ["fp16", "bf16_hw"])
+def test_alone_equals_in_mix(ctx, prec):
+    prec = FP16 if prec == "fp16" else km.Precision(km.KM_LOW_BF16, km.KM_ALPHA_HW, 5.0)
     iters = 6
     reqs = [_req(i, *s) for i, s in enumerate(MIX)]
     # each request alone
     alone = []
     for X, C0 in reqs:
         srv = km.Server(ctx, 1 << 31, max_active=8)
-        t = srv.submit(X, C0, iters, prec=FP16, want_mindist=True)
+        t = srv.submit(X, C0, iters, prec=prec, want_mindist=True)
         assert srv.poll(t, -1) == 0
         alone.append(srv.result(t))
         srv.close()
     # all together
     srv = km.Server(ctx, 1 << 31, max_active=8)
-    tickets = [srv.submit(X, C0, iters, prec=FP16, want_mindist=True) for X, C0 in reqs]
+    tickets = [srv.submit(X, C0, iters, prec=prec, want_mindist=True) for X, C0 in reqs]
     rcs = _wait_all(srv, tickets)
     assert all(rc == 0 for rc in rcs.values()), rcs
     for t, a in zip(tickets, alone):
