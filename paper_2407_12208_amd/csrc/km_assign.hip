@@ -724,7 +724,20 @@ k_assign_pipe(const AssignProb* __restrict__ probs, const int32_t* __restrict__ 
   // (2 gamma_{d+1} at twice the unit roundoff, times the absolute sum).  The
   // block that holds the maximum still beats the seed, so the result is the
   // same as without the seed; only the copies of blocks that cannot win are
-  // skipped.  A hinted pair that the reliability test might flag is not used.
+  // skipped.  A hinted pair that the reliability test might flag is not used
+  // as a seed.  A hinted pair that the test surely flags (even the smallest
+  // FP32 evaluation of W, plus the centre term, reaches the threshold) is
+  // corrected here, once, by the lane whose accumulator rows hold it, and
+  // that accumulator is set to -inf in its block before the block's test:
+  // the sweep then takes its slow path only for other flagged pairs.  (In a
+  // Lloyd round the previous label is often the one flagged pair of a point:
+  // a point close to its centre compared with the norms.)
+  unsigned long long ncorr = 0;
+  // (up to 64 coordinates: at 128 the extra registers would spill)
+  constexpr bool kPreCorrect = FALLBACK && DP <= 64;
+  int xh[NB];  // excluded pair of the lane: block start | register, or -1
+#pragma unroll
+  for (int cb = 0; cb < NB; ++cb) xh[cb] = -1;
   if (P.hint) {
     constexpr float kU2 = 1.0f / 8388608.0f;  // 2 * 2^-24
 #pragma unroll
@@ -766,10 +779,18 @@ k_assign_pipe(const AssignProb* __restrict__ probs, const int32_t* __restrict__ 
         const float delta = 2.0f * (m / (1.0f - m)) * (abs_sum + __builtin_fabsf(ci)) * 1.0625f + 1e-30f;
         const float w = dot + ci;
         if ((w + delta) + caj + delta < hx[cb]) bw[cb] = w - 2.0f * delta;
+        if constexpr (kPreCorrect) {
+          if ((w - delta) + caj - delta >= hx[cb] && (lane >> 5) == ((h >> 2) & 1)) {
+            const float df = (float)sqdist64_call(P.X + (p0 + pl) * d, P.C + (int64_t)h * d, d);
+            ncorr += 1;
+            cd[cb] = df;
+            cj[cb] = h;
+            xh[cb] = (h & ~31) | (4 * ((h & 31) >> 3) + (h & 3));
+          }
+        }
       }
     }
   }
-  unsigned long long ncorr = 0;
   int qn = 0;
   auto flush_queue = [&]() {
     if constexpr (FALLBACK) {
@@ -866,7 +887,20 @@ k_assign_pipe(const AssignProb* __restrict__ probs, const int32_t* __restrict__ 
   };
   // epilogue part 1 (overlaps the next block's MFMAs): block maxima of the
   // test quantity W + ca and of W
-  auto epi1 = [&](const f32x16 (&acc)[NB], int t, int bk, float (&tm)[NB], float (&wm)[NB]) {
+  auto epi1 = [&](f32x16 (&acc)[NB], int t, int bk, float (&tm)[NB], float (&wm)[NB]) {
+    if constexpr (kPreCorrect) {
+      // hinted pairs already corrected: out of this block's test and argmax
+      const int jb = t * CT + bk * 32;
+#pragma unroll
+      for (int cb = 0; cb < NB; ++cb) {
+        const bool here = (xh[cb] & ~31) == jb;
+        if (__ballot(here) != 0) {
+          const int rx = here ? (xh[cb] & 31) : 16;
+#pragma unroll
+          for (int r = 0; r < 16; ++r) acc[cb][r] = r == rx ? -__builtin_inff() : acc[cb][r];
+        }
+      }
+    }
     if constexpr (FALLBACK) {
       f32x16 cav;
 #pragma unroll

@@ -281,12 +281,21 @@ def _hint_cases():
     Cd = C.copy()
     Cd[100:140] = Cd[0:40]
     yield "duplicates", X[:8000], Cd, km.KM_LOW_FP16
+    # every point close to its own centre compared with the norms: the pair
+    # of the (previous) label is the one flagged pair of nearly every point,
+    # and a correct hint has it corrected before the sweep
+    Xl, _, _ = W.blobs(20000, 64, 256, seed=35, center_box=(-50, 50), std_range=(0.1, 2.0))
+    Cl = W.init_centroids(Xl, 256, 36)
+    yield "near_own_centre_fp16", Xl, Cl, km.KM_LOW_FP16
+    yield "near_own_centre_bf16_hw", Xl, Cl, (km.KM_LOW_BF16, km.KM_ALPHA_HW)
+    Xs, _, _ = W.blobs(12000, 40, 100, seed=37, center_box=(-50, 50), std_range=(0.1, 2.0))
+    yield "near_own_centre_d40", Xs, W.init_centroids(Xs, 100, 38), km.KM_LOW_FP16
 
 
-@pytest.mark.parametrize("case", list(range(5)))
+@pytest.mark.parametrize("case", list(range(8)))
 def test_labels_hint_gives_identical_results(ctx, case):
     name, X, C, low = list(_hint_cases())[case]
-    p = prec(low)
+    p = prec(*low) if isinstance(low, tuple) else prec(low)
     Xd, Cd = dev(X), dev(C)
     lab0, md0, sse0, st0 = km.kmeans_assign(ctx, Xd, Cd, p, mindist=True, sse=True)
     n, k = X.shape[0], C.shape[0]
