@@ -135,6 +135,77 @@ def measured_traffic():
         return None
 
 
+def kernel_ms(km, ctx, X, C, prec, reps=3):
+    """Median duration (ms) of the assignment kernel of `reps` passes, from
+    the library's own events on the launch stream."""
+    km.kmeans_assign(ctx, X, C, prec, stats=False)  # workspace and warm-up
+    km.kmeans_timing_enable(ctx, True)
+    for _ in range(reps):
+        km.kmeans_assign(ctx, X, C, prec, stats=False)
+    t = km.kmeans_timing_read(ctx)
+    km.kmeans_timing_enable(ctx, False)
+    import numpy as np
+    return float(np.median(t))
+
+
+def variant_table(km, ctx, torch, np, X, C, Xh, Ch, variants, sample_rows=16384, seed=7):
+    """For each precision variant: assignment-kernel time on the whole input,
+    the fraction of pairs corrected (eq:eta) and the relative error of the
+    per-pair values against the FP64 direct formula on a seeded sample of
+    rows against all centres (values materialised by kmeans_pairwise, the
+    same arithmetic; reference from the CPU oracle)."""
+    import oracle
+    n, d = X.shape
+    k = C.shape[0]
+    rows = np.sort(np.random.default_rng(seed).choice(n, size=min(sample_rows, n), replace=False))
+    ref = oracle.dist_rows(Xh[rows], Ch)
+    Xs = X[torch.from_numpy(rows).cuda()].contiguous()
+    out = {}
+    for name, pr in variants:
+        ms = kernel_ms(km, ctx, X, C, pr)
+        _, _, _, st = km.kmeans_assign(ctx, X, C, pr, stats=True)
+        D, _ = km.kmeans_pairwise(ctx, Xs, C, pr)
+        Dh = D.cpu().numpy().astype(np.float64)
+        del D
+        rel = np.abs(Dh - ref) / np.maximum(ref, 1e-300)
+        out[name] = {"kernel_ms": ms, "pairs_per_s": float(n) * k / (ms * 1e-3),
+                     "eta": st["n_corrected"] / max(st["n_pairs"], 1),
+                     "alpha_used": st["alpha_used"],
+                     "max_rel_err_vs_fp64": float(rel.max()),
+                     "median_rel_err_vs_fp64": float(np.median(rel))}
+        log("variant %s: %.3f ms, eta %.3g, max rel err %.3g" % (
+            name, ms, out[name]["eta"], out[name]["max_rel_err_vs_fp64"]))
+    out["sample"] = "%d seeded rows x all %d centres" % (len(rows), k)
+    return out
+
+
+def dist_variants(km, ctx, torch, W, np, X, C, Xh, Ch):
+    """The distance benchmark's precision variants (full tile + argmin) on
+    the N(0,1) input and on the cancellation-prone input (every coordinate
+    1e3 + 1e-2 z)."""
+    P = km.Precision
+    variants = (("fp16_fp64", P(km.KM_LOW_FP16)),
+                ("fp16_fp64_alg_alpha", P(km.KM_LOW_FP16, km.KM_ALPHA_PAPER_ALG)),
+                ("bf16_fp64", P(km.KM_LOW_BF16)),
+                ("bf16_fp64_hw_alpha", P(km.KM_LOW_BF16, km.KM_ALPHA_HW)),
+                ("fp32_fp64", P(km.KM_LOW_FP32)),
+                ("fp16_uniform", P(km.KM_LOW_FP16, km.KM_ALPHA_NONE)),
+                ("bf16_uniform", P(km.KM_LOW_BF16, km.KM_ALPHA_NONE)),
+                ("fp32_uniform", P(km.KM_LOW_FP32, km.KM_ALPHA_NONE)),
+                ("fp64_direct", P(km.KM_EXACT64)))
+    out = {"normal": variant_table(km, ctx, torch, np, X, C, Xh, Ch, variants)}
+    cfg = W.DIST_BENCH
+    log("cancellation variant: generating %d x %d" % (cfg["n"], cfg["d"]))
+    Xc, Cc = W.cancellation_pair(cfg["n"], cfg["k"], cfg["d"], cfg["seed"])
+    Xcd = torch.from_numpy(Xc).cuda()
+    Ccd = torch.from_numpy(Cc).cuda()
+    cvariants = tuple(v for v in variants if v[0] in ("fp16_fp64", "bf16_fp64", "fp16_uniform",
+                                                      "bf16_uniform", "fp32_uniform", "fp64_direct"))
+    out["cancellation"] = variant_table(km, ctx, torch, np, Xcd, Ccd, Xc, Cc, cvariants)
+    del Xcd, Ccd
+    return out
+
+
 def large_bench(km, ctx, torch, W, np):
     """Large clustering: 2,000,000 x 64 points from 1,024 blobs (centres
     U[-50,50]^64, per-blob std log-uniform in [0.1, 2]), 50 Lloyd rounds and
@@ -233,6 +304,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-extra", action="store_true", help="skip the extra measurements")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--no-variants", action="store_true",
+                    help="skip the precision-variant table of the distance benchmark")
     ap.add_argument("--no-large", action="store_true",
                     help="skip the large-clustering measurement")
     ap.add_argument("--batch-problems", type=int, default=256,
@@ -345,6 +418,8 @@ def main():
         extra["fp64_direct_pairs_per_s"] = pairs / (ms64 * 1e-3)
         extra["speedup_assign_vs_fp64_direct"] = ms64 / kern_avg_ms
         extra["fp64_direct_frac_of_fp64_peak"] = (3.0 * n * k * d / (ms64 * 1e-3) / 1e12) / FP64_PEAK_TFLOPS
+        if not args.no_variants:
+            extra["distance_variants"] = dist_variants(km, ctx, torch, W, np, X, Ca, Xh, Ch)
         # single Lloyd solve: 20,000 x 32, 16 blobs, 20 rounds + final pass
         cs = W.LLOYD_SMALL
         Xs, _, _ = W.blobs(cs["n"], cs["d"], cs["k"], cs["seed"])

@@ -30,7 +30,11 @@
  *    after the device work ran: they are returned when the call waits for the
  *    stream (KM_SYNC or stats != NULL) and stored in stats->data_status.
  *  - Nothing throws across this ABI, nothing aborts, nothing prints.
- *  - A context is used by one host thread at a time.  The server functions
+ *  - A context is used by one host thread at a time.  Its calls may use
+ *    different streams: the device work of each call that uses the context's
+ *    workspace is ordered after that of the previous such call on the same
+ *    context (an event recorded at the end of every call, waited for on the
+ *    next call's stream when the stream differs).  The server functions
  *    (kmeans_submit, kmeans_poll, kmeans_cancel) are thread-safe.
  */
 #ifndef KMEANS_MI355X_H

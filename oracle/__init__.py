@@ -85,6 +85,9 @@ def lib():
             L.oracle_mp_rows.restype = i64
             L.oracle_mp_rows.argtypes = [P, i64, i32, P, i32, i32, dbl,
                                          P, P, P, P, P, P]
+            L.oracle_mp_scan.restype = i32
+            L.oracle_mp_scan.argtypes = [P, i64, i32, P, i32, i32, dbl, i32, P,
+                                         P, P, P, P, P, P, P, P]
             L.oracle_mp_count.restype = None
             L.oracle_mp_count.argtypes = [P, i64, i32, P, i32, i32, dbl, P]
             L.oracle_num_threads.restype = i32
@@ -270,6 +273,42 @@ def mp_rows(X, C, fmt: int, alpha: float):
                                 _ptr(out["B"]), _ptr(cls))
     out["cls"] = cls
     out["n_bad"] = int(nbad)
+    return out
+
+
+def mp_scan(X, C, fmt: int, alpha: float, labels=()):
+    """The per-row quantities of the parity contract over all pairs of X
+    against C, streamed (nothing of size m x k is kept): O1's label ``j1``,
+    ``dj1`` = its distance, ``Bj1`` = its O4 bound, ``lo`` = min over the
+    other centres of (dist - B), ``d2`` = min over the other centres of
+    dist, and for each array in ``labels`` the
+    distance ``dlab[t]`` and bound ``Blab[t]`` at that label; ``counts`` =
+    (surely corrected, ambiguous, surely kept, overflow) over all pairs.
+    ``fmt`` 0 / 1 = FP16 / BF16 with threshold ``alpha`` (< 0: never
+    corrected); ``fmt`` 3 = every pair by the FP64 direct formula, compared
+    in FP64 (B = 2 gamma_{d+2}(u_64) dist)."""
+    X, C = _f32(X), _f32(C)
+    m, d = X.shape
+    k = C.shape[0]
+    labs = [np.ascontiguousarray(l, dtype=np.int32).ravel() for l in labels]
+    for l in labs:
+        if l.shape[0] != m:
+            raise ValueError("label array of length %d for %d rows" % (l.shape[0], m))
+    nlab = len(labs)
+    lab_arr = np.concatenate(labs) if nlab else np.zeros(1, dtype=np.int32)
+    out = dict(j1=np.empty(m, dtype=np.int32), dj1=np.empty(m), Bj1=np.empty(m),
+               lo=np.empty(m), d2=np.empty(m), dlab=np.empty((max(nlab, 1), m)),
+               Blab=np.empty((max(nlab, 1), m)), counts=np.zeros(4, dtype=np.int64))
+    a = float(alpha) if np.isfinite(alpha) else 1e300
+    rc = lib().oracle_mp_scan(_ptr(X), m, d, _ptr(C), k, int(fmt), a, nlab,
+                              _ptr(lab_arr), _ptr(out["j1"]), _ptr(out["dj1"]),
+                              _ptr(out["Bj1"]), _ptr(out["lo"]), _ptr(out["d2"]),
+                              _ptr(out["dlab"]),
+                              _ptr(out["Blab"]), _ptr(out["counts"]))
+    if rc != 0:
+        raise MemoryError("oracle_mp_scan failed")
+    out["dlab"] = out["dlab"][:nlab]
+    out["Blab"] = out["Blab"][:nlab]
     return out
 
 

@@ -334,6 +334,102 @@ int oracle_lloyd(const float *X, int64_t n, int d, int k, float *C, int max_iter
  * Every output pointer except dist is nullable.  Returns the number of pairs
  * whose inputs overflow the low format (those get cls = -2, B = inf).
  */
+/* Quantised centres of O4: C~ (k x d, as doubles), ||c~_j||^2 and an
+ * overflow flag per centre.  Returns 0, or -1 when out of memory. */
+typedef struct {
+  double *Ct;
+  double *nc;
+  int *bad;
+} mp_centres;
+
+static int mp_centres_make(const float *C, int k, int d, int fmt, mp_centres *mc) {
+  mc->Ct = (double *)malloc(sizeof(double) * (size_t)k * (size_t)d);
+  mc->nc = (double *)malloc(sizeof(double) * (size_t)k);
+  mc->bad = (int *)calloc((size_t)k, sizeof(int));
+  if (!mc->Ct || !mc->nc || !mc->bad) {
+    free(mc->Ct);
+    free(mc->nc);
+    free(mc->bad);
+    return -1;
+  }
+  for (int j = 0; j < k; ++j) {
+    double s = 0.0;
+    for (int l = 0; l < d; ++l) {
+      double v = oracle_round_low(C[(int64_t)j * d + l], fmt);
+      if (isinf(v) || isnan(v)) mc->bad[j] = 1;
+      mc->Ct[(int64_t)j * d + l] = v;
+      s += v * v;
+    }
+    mc->nc[j] = s;
+  }
+  return 0;
+}
+
+static void mp_centres_free(mp_centres *mc) {
+  free(mc->Ct);
+  free(mc->nc);
+  free(mc->bad);
+}
+
+/* O4 quantities of one pair (x, c_j): dist, q, S, A, class and bound B as
+ * described above.  xt is x~ (doubles), nx = ||x~||^2, xbad = x~ overflows. */
+typedef struct {
+  double dist, q, S, A, B;
+  int8_t cls;
+} mp_pair;
+
+static mp_pair mp_pair_eval(const float *x, const double *xt, double nx, int xbad,
+                            const float *c, const mp_centres *mc, int j, int d,
+                            double alpha, double gp, double g64, double u32) {
+  mp_pair r;
+  const double *ct = mc->Ct + (int64_t)j * d;
+  r.dist = oracle_sqdist(x, c, d);
+  double q = 0.0, P = 0.0;
+  for (int l = 0; l < d; ++l) {
+    double diff = xt[l] - ct[l];
+    q += diff * diff;
+    P += fabs(xt[l]) * fabs(ct[l]);
+  }
+  r.q = q;
+  r.S = nx + mc->nc[j];
+  r.A = gp * (r.S + 2.0 * P);
+  double Bk = fabs(q - r.dist) + r.A + g64 * r.dist;
+  double Bc = 2.0 * u32 * r.dist;
+  if (xbad || mc->bad[j]) {
+    r.cls = -2;
+    r.B = INFINITY;
+  } else if (alpha < 0.0) {
+    r.cls = 1;
+    r.B = Bk;
+  } else {
+    double margin = q - alpha * r.S;
+    double band = (1.0 + alpha) * r.A;
+    if (margin < -band) {
+      r.cls = -1;
+      r.B = Bc;
+    } else if (margin > band) {
+      r.cls = 1;
+      r.B = Bk;
+    } else {
+      r.cls = 0;
+      r.B = Bk > Bc ? Bk : Bc;
+    }
+  }
+  return r;
+}
+
+/* x~ = RNE_fmt(x) into xt; returns ||x~||^2 and sets *bad on overflow. */
+static double mp_round_row(const float *x, int d, int fmt, double *xt, int *bad) {
+  double nx = 0.0;
+  *bad = 0;
+  for (int l = 0; l < d; ++l) {
+    xt[l] = oracle_round_low(x[l], fmt);
+    if (isinf(xt[l]) || isnan(xt[l])) *bad = 1;
+    nx += xt[l] * xt[l];
+  }
+  return nx;
+}
+
 int64_t oracle_mp_rows(const float *X, int64_t m, int d, const float *C, int k,
                        int fmt, double alpha, double *dist, double *q_out,
                        double *S_out, double *A_out, double *B_out,
@@ -341,87 +437,119 @@ int64_t oracle_mp_rows(const float *X, int64_t m, int d, const float *C, int k,
   double u32 = oracle_unit_roundoff(2), u64 = oracle_unit_roundoff(3);
   double gp = oracle_gamma((double)(d + 4), 2.0 * u32);
   double g64 = oracle_gamma((double)(d + 2), u64);
-  double *Ct = (double *)malloc(sizeof(double) * (size_t)k * (size_t)d);
-  double *nc = (double *)malloc(sizeof(double) * (size_t)k);
-  int *cbad = (int *)calloc((size_t)k, sizeof(int));
-  if (!Ct || !nc || !cbad) {
-    free(Ct);
-    free(nc);
-    free(cbad);
-    return -1;
-  }
-  for (int j = 0; j < k; ++j) {
-    double s = 0.0;
-    for (int l = 0; l < d; ++l) {
-      double v = oracle_round_low(C[(int64_t)j * d + l], fmt);
-      if (isinf(v) || isnan(v)) cbad[j] = 1;
-      Ct[(int64_t)j * d + l] = v;
-      s += v * v;
-    }
-    nc[j] = s;
-  }
+  mp_centres mc;
+  if (mp_centres_make(C, k, d, fmt, &mc) != 0) return -1;
   int64_t nbad = 0;
 #pragma omp parallel for schedule(static) reduction(+ : nbad)
   for (int64_t i = 0; i < m; ++i) {
     const float *x = X + i * (int64_t)d;
     double *xt = (double *)malloc(sizeof(double) * (size_t)d);
-    double nx = 0.0;
-    int xbad = 0;
-    for (int l = 0; l < d; ++l) {
-      xt[l] = oracle_round_low(x[l], fmt);
-      if (isinf(xt[l]) || isnan(xt[l])) xbad = 1;
-      nx += xt[l] * xt[l];
-    }
+    int xbad;
+    double nx = mp_round_row(x, d, fmt, xt, &xbad);
     for (int j = 0; j < k; ++j) {
       int64_t o = i * (int64_t)k + j;
-      const double *ct = Ct + (int64_t)j * d;
-      double dd = oracle_sqdist(x, C + (int64_t)j * d, d);
-      double q = 0.0, P = 0.0;
-      for (int l = 0; l < d; ++l) {
-        double diff = xt[l] - ct[l];
-        q += diff * diff;
-        P += fabs(xt[l]) * fabs(ct[l]);
-      }
-      double S = nx + nc[j];
-      double A = gp * (S + 2.0 * P);
-      int8_t cls;
-      double B;
-      double Bk = fabs(q - dd) + A + g64 * dd;
-      double Bc = 2.0 * u32 * dd;
-      if (xbad || cbad[j]) {
-        cls = -2;
-        B = INFINITY;
-        nbad += 1;
-      } else if (alpha < 0.0) {
-        cls = 1;
-        B = Bk;
-      } else {
-        double margin = q - alpha * S;
-        double band = (1.0 + alpha) * A;
-        if (margin < -band) {
-          cls = -1;
-          B = Bc;
-        } else if (margin > band) {
-          cls = 1;
-          B = Bk;
-        } else {
-          cls = 0;
-          B = Bk > Bc ? Bk : Bc;
-        }
-      }
-      dist[o] = dd;
-      if (q_out) q_out[o] = q;
-      if (S_out) S_out[o] = S;
-      if (A_out) A_out[o] = A;
-      if (B_out) B_out[o] = B;
-      if (cls_out) cls_out[o] = cls;
+      mp_pair r = mp_pair_eval(x, xt, nx, xbad, C + (int64_t)j * d, &mc, j, d,
+                               alpha, gp, g64, u32);
+      if (r.cls == -2) nbad += 1;
+      dist[o] = r.dist;
+      if (q_out) q_out[o] = r.q;
+      if (S_out) S_out[o] = r.S;
+      if (A_out) A_out[o] = r.A;
+      if (B_out) B_out[o] = r.B;
+      if (cls_out) cls_out[o] = r.cls;
     }
     free(xt);
   }
-  free(Ct);
-  free(nc);
-  free(cbad);
+  mp_centres_free(&mc);
   return nbad;
+}
+
+/* The per-row quantities of the parity contract without materialising the
+ * m x k pairs (same pair arithmetic as oracle_mp_rows).  For every row i:
+ *   j1[i]   = smallest index attaining min_j dist_ij (O1's label)
+ *   dj1[i]  = dist_{i j1},  Bj1[i] = B_{i j1}
+ *   lo[i]   = min_{j != j1} (dist_ij - B_ij)   (+inf when k = 1)
+ *   d2[i]   = min_{j != j1} dist_ij            (+inf when k = 1)
+ * and for each of the nlab given label arrays (labs[t*m + i], t < nlab):
+ *   dlab[t*m + i] = dist_{i, lab},  Blab[t*m + i] = B_{i, lab}
+ * (labels outside [0,k) give NaN).  The label gate of row i is
+ * lo[i] > dj1[i] + Bj1[i].  counts[0..3] receive the class counts over all
+ * pairs (surely corrected, ambiguous, surely kept, overflow).
+ * fmt = 3 (no low precision: every pair is the FP64 direct value compared in
+ * FP64) uses B = 2 gamma_{d+2}(u_64) dist and counts every pair as corrected.
+ * Returns 0, or -1 when out of memory. */
+int oracle_mp_scan(const float *X, int64_t m, int d, const float *C, int k,
+                   int fmt, double alpha, int nlab, const int32_t *labs,
+                   int32_t *j1_out, double *dj1_out, double *Bj1_out,
+                   double *lo_out, double *d2_out, double *dlab, double *Blab,
+                   int64_t *counts) {
+  double u32 = oracle_unit_roundoff(2), u64 = oracle_unit_roundoff(3);
+  double gp = oracle_gamma((double)(d + 4), 2.0 * u32);
+  double g64 = oracle_gamma((double)(d + 2), u64);
+  mp_centres mc = {NULL, NULL, NULL};
+  if (fmt != 3 && mp_centres_make(C, k, d, fmt, &mc) != 0) return -1;
+  int64_t c0 = 0, c1 = 0, c2 = 0, c3 = 0;
+  int fail = 0;
+#pragma omp parallel reduction(+ : c0, c1, c2, c3) reduction(| : fail)
+  {
+    double *xt = (double *)malloc(sizeof(double) * (size_t)d);
+    double *dist = (double *)malloc(sizeof(double) * (size_t)k);
+    double *B = (double *)malloc(sizeof(double) * (size_t)k);
+    if (!xt || !dist || !B) fail = 1;
+#pragma omp for schedule(dynamic, 64)
+    for (int64_t i = 0; i < m; ++i) {
+      if (fail) continue;
+      const float *x = X + i * (int64_t)d;
+      if (fmt == 3) {
+        for (int j = 0; j < k; ++j) {
+          dist[j] = oracle_sqdist(x, C + (int64_t)j * d, d);
+          B[j] = 2.0 * g64 * dist[j];
+        }
+        c0 += k;
+      } else {
+        int xbad;
+        double nx = mp_round_row(x, d, fmt, xt, &xbad);
+        for (int j = 0; j < k; ++j) {
+          mp_pair r = mp_pair_eval(x, xt, nx, xbad, C + (int64_t)j * d, &mc, j, d,
+                                   alpha, gp, g64, u32);
+          dist[j] = r.dist;
+          B[j] = r.B;
+          if (r.cls == -1) c0++;
+          else if (r.cls == 0) c1++;
+          else if (r.cls == 1) c2++;
+          else c3++;
+        }
+      }
+      int best = 0;
+      for (int j = 1; j < k; ++j)
+        if (dist[j] < dist[best]) best = j;
+      double lo = INFINITY, d2 = INFINITY;
+      for (int j = 0; j < k; ++j) {
+        if (j == best) continue;
+        if (dist[j] - B[j] < lo) lo = dist[j] - B[j];
+        if (dist[j] < d2) d2 = dist[j];
+      }
+      j1_out[i] = best;
+      d2_out[i] = d2;
+      dj1_out[i] = dist[best];
+      Bj1_out[i] = B[best];
+      lo_out[i] = lo;
+      for (int t = 0; t < nlab; ++t) {
+        int32_t lab = labs[(int64_t)t * m + i];
+        dlab[(int64_t)t * m + i] = (lab >= 0 && lab < k) ? dist[lab] : NAN;
+        Blab[(int64_t)t * m + i] = (lab >= 0 && lab < k) ? B[lab] : NAN;
+      }
+    }
+    free(xt);
+    free(dist);
+    free(B);
+  }
+  if (fmt != 3) mp_centres_free(&mc);
+  counts[0] = c0;
+  counts[1] = c1;
+  counts[2] = c2;
+  counts[3] = c3;
+  return fail ? -1 : 0;
 }
 
 /* Counts of the O4 classes over all pairs, without materialising them:

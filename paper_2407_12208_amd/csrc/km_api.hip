@@ -278,6 +278,26 @@ hipError_t run_reduce(km_context_impl* ctx, const std::vector<ReduceProb>& probs
   return launch_reduce_parts((const ReduceProb*)dp, (int)probs.size(), st);
 }
 
+hipError_t read_results(km_context_impl* ctx, const std::vector<const KResult*>& src, KResult* out,
+                        hipStream_t st) {
+  const int cap = km_context_impl::kMaxResults;
+  hipError_t e = ctx->arena.ensure(sizeof(KResult) * (size_t)cap);
+  if (e != hipSuccess) return e;
+  ctx->arena.reset();
+  KResult* dst = ctx->arena.take<KResult>((size_t)cap);
+  for (size_t s0 = 0; s0 < src.size(); s0 += (size_t)cap) {
+    const int cnt = (int)std::min(src.size() - s0, (size_t)cap);
+    void* dsrc = ctx->up.put(src.data() + s0, sizeof(const KResult*) * (size_t)cnt, st);
+    if (!dsrc) return hipErrorOutOfMemory;
+    e = launch_gather_results((const KResult* const*)dsrc, cnt, dst, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(ctx->h_result, dst, sizeof(KResult) * (size_t)cnt, hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return e;
+    memcpy(out + s0, ctx->h_result, sizeof(KResult) * (size_t)cnt);
+  }
+  return hipSuccess;
+}
+
 void plan_update(Plan& pl, int64_t n, int d, int k) {
   const int ntiles = (int)((n + kUpdTile - 1) / kUpdTile);
   pl.add<int32_t>((size_t)k * ntiles);  // hist
@@ -394,7 +414,8 @@ int32_t kmeans_context_create(int32_t device, km_context** out) {
   if (c->up.init(8u << 20) != hipSuccess ||
       hipHostMalloc(reinterpret_cast<void**>(&c->h_scalar), 64, hipHostMallocDefault) != hipSuccess ||
       hipHostMalloc(reinterpret_cast<void**>(&c->h_result), sizeof(KResult) * km_context_impl::kMaxResults,
-                    hipHostMallocDefault) != hipSuccess) {
+                    hipHostMallocDefault) != hipSuccess ||
+      hipEventCreateWithFlags(&c->ws_event, hipEventDisableTiming) != hipSuccess) {
     kmeans_context_destroy(c);
     return KM_ERR_OOM;
   }
@@ -427,6 +448,7 @@ int32_t kmeans_context_destroy(km_context* c) {
   (void)hipSetDevice(c->device);
   (void)hipDeviceSynchronize();
   for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
+  if (c->ws_event) (void)hipEventDestroy(c->ws_event);
   c->up.destroy();
   if (c->arena.base) (void)hipFree(c->arena.base);
   if (c->h_scalar) (void)hipHostFree(c->h_scalar);
@@ -583,6 +605,8 @@ int32_t kmeans_assign(km_context* ctx, const float* X, int64_t n, int32_t d, con
   if (v != KM_OK) return v;
   hipStream_t st = (hipStream_t)stream;
   KM_HIP(hipSetDevice(ctx->device));
+  WorkspaceUse ws_use(ctx, st);
+  KM_HIP(ws_use.err);
   AssignPlan a = plan_assign(p, n, d, k);
   Plan pl;
   plan_pass(pl, a);
@@ -608,6 +632,8 @@ int32_t kmeans_pairwise(km_context* ctx, const float* X, int64_t m, int32_t d, c
   if (v != KM_OK) return v;
   hipStream_t st = (hipStream_t)stream;
   KM_HIP(hipSetDevice(ctx->device));
+  WorkspaceUse ws_use(ctx, st);
+  KM_HIP(ws_use.err);
   AssignPlan a = plan_assign(p, m, d, k);
   Plan pl;
   plan_pass(pl, a);
@@ -637,6 +663,8 @@ int32_t kmeans_update(km_context* ctx, const float* X, int64_t n, int32_t d, con
   if (n < 1 || n > (int64_t)INT32_MAX - 1024 || d < 1 || k < 1 || k > 65536) return KM_ERR_ARG;
   hipStream_t st = (hipStream_t)stream;
   KM_HIP(hipSetDevice(ctx->device));
+  WorkspaceUse ws_use(ctx, st);
+  KM_HIP(ws_use.err);
   Plan pl;
   plan_update(pl, n, d, k);
   pl.add<int>(1);
@@ -676,6 +704,8 @@ int32_t kmeans_lloyd(km_context* ctx, const float* X, int64_t n, int32_t d, int3
   if (v != KM_OK) return v;
   hipStream_t st = (hipStream_t)stream;
   KM_HIP(hipSetDevice(ctx->device));
+  WorkspaceUse ws_use(ctx, st);
+  KM_HIP(ws_use.err);
   AssignPlan a = plan_assign(p, n, d, k);
   Plan pl;
   plan_pass(pl, a);
@@ -857,6 +887,8 @@ extern "C" int32_t kmeans_solve_batch(km_context* ctx, km_problem* probs, int32_
   }
   hipStream_t st = (hipStream_t)stream;
   KM_HIP(hipSetDevice(ctx->device));
+  WorkspaceUse ws_use(ctx, st);
+  KM_HIP(ws_use.err);
   std::vector<BatchState> S(count);
   Plan pl;
   for (int i = 0; i < count; ++i) {

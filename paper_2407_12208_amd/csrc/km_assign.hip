@@ -1782,6 +1782,24 @@ hipError_t launch_zero_words(void* p, size_t bytes, hipStream_t st) {
   return hipGetLastError();
 }
 
+// Copies the result records of many problems into one contiguous array (one
+// device-to-host copy then reads them all).
+__global__ void __launch_bounds__(256) k_gather_results(const KResult* const* __restrict__ src, int count,
+                                                        KResult* __restrict__ dst) {
+  constexpr int W = (int)(sizeof(KResult) / 4);
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= count * W) return;
+  const int r = i / W, w = i - r * W;
+  as_global(reinterpret_cast<uint32_t*>(dst))[i] = as_global(reinterpret_cast<const uint32_t*>(src[r]))[w];
+}
+
+hipError_t launch_gather_results(const KResult* const* dsrc, int count, KResult* ddst, hipStream_t st) {
+  const int words = count * (int)(sizeof(KResult) / 4);
+  if (words == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_gather_results, dim3((words + 255) / 256), dim3(256), 0, st, dsrc, count, ddst);
+  return hipGetLastError();
+}
+
 hipError_t launch_reduce_parts(const ReduceProb* dprobs, int nprob, hipStream_t st) {
   hipLaunchKernelGGL(k_reduce_parts, dim3(nprob), dim3(256), 0, st, dprobs);
   return hipGetLastError();

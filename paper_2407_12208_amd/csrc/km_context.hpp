@@ -77,11 +77,33 @@ struct km_context_impl {
   double* h_scalar = nullptr;     // pinned: shift read-back
   KResult* h_result = nullptr;    // pinned: result read-back (up to kMaxResults)
   static constexpr int kMaxResults = 4096;
+  // Workspace ordering across streams: every call that uses the arena or
+  // the result records waits (on its own stream) for the last such call's
+  // work, whatever stream that call used, and records its own end here.
+  hipEvent_t ws_event = nullptr;
+  hipStream_t ws_stream = nullptr;
+  bool ws_valid = false;
   // kernel timing
   bool timing = false;
   std::vector<hipEvent_t> ev_pool;  // pairs: [2i] start, [2i+1] stop
   int ev_used = 0;                  // pairs recorded since enable
   hipEvent_t timing_event(int i);
+};
+
+// Scope of one entry point's use of the context workspace on stream st.
+struct WorkspaceUse {
+  km_context_impl* c;
+  hipStream_t st;
+  hipError_t err = hipSuccess;
+  WorkspaceUse(km_context_impl* ctx, hipStream_t s) : c(ctx), st(s) {
+    if (c->ws_valid && c->ws_stream != st) err = hipStreamWaitEvent(st, c->ws_event, 0);
+  }
+  ~WorkspaceUse() {
+    if (c->ws_event && hipEventRecord(c->ws_event, st) == hipSuccess) {
+      c->ws_stream = st;
+      c->ws_valid = true;
+    }
+  }
 };
 
 // Threshold alpha for (prec, d): -1 = no fallback, +inf = always correct.
@@ -120,6 +142,12 @@ hipError_t run_assign(km_context_impl* ctx, const AssignPlan& shape, int mode,
                       const std::vector<AssignProb>& probs, const std::vector<int>& nwgs, hipStream_t st);
 hipError_t run_reduce(km_context_impl* ctx, const std::vector<ReduceProb>& probs, hipStream_t st);
 hipError_t run_update(km_context_impl* ctx, const std::vector<UpdateProb>& probs, hipStream_t st);
+
+// Reads the result records at src (device) into out (host): one gather
+// launch and one copy per kMaxResults records, then waits for st.  Uses the
+// context's arena.
+hipError_t read_results(km_context_impl* ctx, const std::vector<const KResult*>& src, KResult* out,
+                        hipStream_t st);
 
 // Workspace sizes of one problem's centre update.
 void plan_update(Plan& pl, int64_t n, int d, int k);

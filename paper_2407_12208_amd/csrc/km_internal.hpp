@@ -133,6 +133,7 @@ hipError_t launch_assign_small(int low, int xd, bool fallback, const AssignProb*
 hipError_t launch_assign_direct64(bool cmp64, int mode, const AssignProb* dprobs, const int32_t* dstart,
                                   int nprob, int nwg, hipStream_t st);
 hipError_t launch_reduce_parts(const ReduceProb* dprobs, int nprob, hipStream_t st);
+hipError_t launch_gather_results(const KResult* const* dsrc, int count, KResult* ddst, hipStream_t st);
 hipError_t launch_zero_words(void* p, size_t bytes, hipStream_t st);  // bytes rounded up to 4
 hipError_t launch_quantize(int low, const float* in, int64_t count, uint16_t* out, hipStream_t st);
 

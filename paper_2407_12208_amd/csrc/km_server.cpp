@@ -87,7 +87,10 @@ class RangeAlloc {
   std::map<size_t, size_t> free_;
 };
 
-enum class ReqState { Queued, Active, Done };
+// Queued: in the arrival queue.  Admitting: taken off the queue by the
+// scheduler, its data being copied in (the lock is not held meanwhile).
+// Active: in the running set.  Done: finished, failed or cancelled.
+enum class ReqState { Queued, Admitting, Active, Done };
 
 struct Request {
   uint64_t ticket;
@@ -101,7 +104,7 @@ struct Request {
   BatchState bs{};
   ReqState state = ReqState::Queued;
   int32_t status = KM_PENDING;  // final status once Done
-  bool cancel = false;
+  std::atomic<bool> cancel{false};  // set by kmeans_cancel, read by the scheduler
   bool final_enqueued = false;
 };
 
@@ -136,7 +139,7 @@ struct km_server {
   std::thread thr;
   void loop();
   bool admit_one(km::Request* r);
-  void retire(km::Request* r, int32_t status, bool copy_results);
+  void retire(km::Request* r, int32_t status, bool copy_results, const km::KResult* res);
 };
 
 using namespace km;
@@ -186,7 +189,7 @@ bool km_server::admit_one(Request* r) {
   return true;
 }
 
-void km_server::retire(Request* r, int32_t status, bool copy_results) {
+void km_server::retire(Request* r, int32_t status, bool copy_results, const KResult* res_in) {
   // results: compute stream is idle here (the round was synchronised)
   if (copy_results) {
     const km_problem& h = r->host;
@@ -203,7 +206,8 @@ void km_server::retire(Request* r, int32_t status, bool copy_results) {
   }
   if (r->host.stats) {
     KResult res{};
-    (void)hipMemcpy(&res, r->bs.bufs.result, sizeof(KResult), hipMemcpyDeviceToHost);
+    if (res_in) res = *res_in;
+    else (void)hipMemcpy(&res, r->bs.bufs.result, sizeof(KResult), hipMemcpyDeviceToHost);
     km_stats* o = r->host.stats;
     o->n_corrected = r->plan.route == Route::Direct64Exact ? 0 : res.n_corrected;
     o->n_pairs = res.n_pairs;
@@ -250,46 +254,75 @@ void km_server::loop() {
     for (Request* r : active)
       if (!r->cancel && r->bs.done && std::find(fin.begin(), fin.end(), &r->bs) != fin.end())
         r->final_enqueued = true;
-    // ---- 2. admission while the round runs
+    // ---- 2. admission while the round runs.  The head request leaves the
+    // queue (state Admitting) before the lock is released for its copies,
+    // so a concurrent cancel only flags it; a request that does not fit goes
+    // back to the head of the queue (FIFO: no overtaking).
     std::vector<Request*> admitted;
     {
       std::unique_lock<std::mutex> lk(mu);
       while (!queued.empty() && (int)(active.size() + admitted.size()) < max_active) {
         Request* r = queued.front();
+        queued.pop_front();
+        r->state = ReqState::Admitting;
         lk.unlock();
         const bool ok = admit_one(r);
         lk.lock();
-        if (!ok) break;  // wait for memory to free up (FIFO: no overtaking)
-        queued.pop_front();
+        if (!ok) {
+          if (r->cancel.load()) {
+            r->status = KM_ERR_CANCELLED;
+            r->state = ReqState::Done;
+            cv_done.notify_all();
+            continue;
+          }
+          r->state = ReqState::Queued;
+          queued.push_front(r);
+          break;
+        }
         r->state = ReqState::Active;
         admitted.push_back(r);
       }
     }
     if (!admitted.empty()) (void)hipStreamSynchronize(copy);
-    // ---- 3. wait for the round, read results, retire
+    for (size_t i = 0; i < admitted.size();) {  // cancelled while admitted
+      Request* r = admitted[i];
+      if (r->cancel.load()) {
+        retire(r, KM_ERR_CANCELLED, false, nullptr);
+        admitted.erase(admitted.begin() + (long)i);
+      } else {
+        ++i;
+      }
+    }
+    // ---- 3. wait for the round, read every running request's result
+    // record with one gather and one copy, retire
     hipError_t es = hipStreamSynchronize(compute);
+    std::vector<KResult> res(active.size());
+    if (e == hipSuccess && es == hipSuccess && !active.empty()) {
+      std::vector<const KResult*> src(active.size());
+      for (size_t i = 0; i < active.size(); ++i) src[i] = active[i]->bs.bufs.result;
+      es = read_results(ctx, src, res.data(), compute);
+    }
     std::vector<Request*> keep;
-    for (Request* r : active) {
-      if (r->cancel) {
-        retire(r, KM_ERR_CANCELLED, false);
+    for (size_t i = 0; i < active.size(); ++i) {
+      Request* r = active[i];
+      if (r->cancel.load()) {
+        retire(r, KM_ERR_CANCELLED, false, nullptr);
         continue;
       }
       if (e != hipSuccess || es != hipSuccess) {
-        retire(r, KM_ERR_DEVICE, false);
+        retire(r, KM_ERR_DEVICE, false, nullptr);
         continue;
       }
-      KResult res{};
-      (void)hipMemcpy(&res, r->bs.bufs.result, sizeof(KResult), hipMemcpyDeviceToHost);
-      const int32_t ds = status_from_bits(res.status);
+      const int32_t ds = status_from_bits(res[i].status);
       if (ds != KM_OK) {
-        retire(r, ds, false);
+        retire(r, ds, false, &res[i]);
         continue;
       }
       if (r->final_enqueued) {
-        retire(r, KM_OK, true);
+        retire(r, KM_OK, true, &res[i]);
         continue;
       }
-      if (!r->bs.done && r->host.tol > 0.0 && r->bs.it > 0 && res.shift < r->host.tol) r->bs.done = true;
+      if (!r->bs.done && r->host.tol > 0.0 && r->bs.it > 0 && res[i].shift < r->host.tol) r->bs.done = true;
       keep.push_back(r);
     }
     active.swap(keep);
@@ -377,7 +410,7 @@ int32_t kmeans_cancel(km_server* s, uint64_t ticket) {
     r->state = ReqState::Done;
     s->cv_done.notify_all();
   } else {
-    r->cancel = true;  // retired at the end of the current round
+    r->cancel.store(true);  // Admitting or Active: retired by the scheduler
   }
   return KM_OK;
 }

@@ -114,3 +114,59 @@ def check_pairwise(X, C, fmt, alpha, D, flagged):
     return dict(n_flagged=int(fl.sum()), n_sure=int((cls == -1).sum()),
                 n_amb=int((cls == 0).sum()), max_rel_err=float(rel.max()),
                 max_rel_err_kept=float(rel[kept].max()) if kept.any() else 0.0)
+
+
+def scan_rows(X, C, fmt, alpha, label_arrays):
+    """O4 over every pair of X against C, streamed (oracle.mp_scan), with the
+    oracle quantities at each of the given GPU label arrays."""
+    return oracle.mp_scan(X, C, fmt, -1.0 if alpha is None else alpha, label_arrays)
+
+
+def check_assignment_scan(scan, t, labels, mindist, sse, n_corrected, *, bound="mp",
+                          d=None, min_coverage=0.0, check_sandwich=True):
+    """(i)-(iii) over ALL rows from a streamed scan (``scan_rows``); ``t``
+    selects which of the scan's label arrays ``labels`` is.  ``bound="mp"``
+    applies O4's bounds (fmt and alpha of the scan); ``bound="fp64"`` the
+    plain FP64 direct formula compared in FP64 (B = 2 gamma_{d+2}(u_64)
+    dist, ``d`` required)."""
+    lab = np.asarray(labels).astype(np.int64)
+    j1 = scan["j1"].astype(np.int64)
+    dj1 = scan["dj1"]
+    d_lab = scan["dlab"][t]
+    if bound == "fp64":
+        g = 2 * oracle.gamma(d + 2, oracle.unit_roundoff(3))
+        Bj1 = g * dj1
+        Blab = g * d_lab
+        gated = scan["d2"] * (1 - g) > dj1 * (1 + g)
+    else:
+        Bj1 = scan["Bj1"]
+        Blab = scan["Blab"][t]
+        gated = scan["lo"] > dj1 + Bj1
+    assert np.all(np.isfinite(d_lab)), "label out of range"
+    bad = np.nonzero(gated & (lab != j1))[0]
+    assert bad.size == 0, "gated label mismatch at rows %s (gpu %s, oracle %s)" % (
+        bad[:5], lab[bad[:5]], j1[bad[:5]])
+    coverage = float(gated.mean())
+    assert coverage >= min_coverage, "gate coverage %.5f < %.5f" % (coverage, min_coverage)
+    slack = dj1 + Blab + Bj1
+    far = np.nonzero(d_lab > slack * (1 + 1e-12) + 1e-300)[0]
+    assert far.size == 0, "label not near-optimal at rows %s" % far[:5]
+    rep = dict(coverage=coverage, n_rows=len(lab), n_ungated=int((~gated).sum()),
+               n_diff=int((lab != j1).sum()))
+    if mindist is not None:
+        md = np.asarray(mindist).astype(np.float64)
+        err = np.abs(md - d_lab)
+        tol = DIST_RTOL * d_lab + 1e-30
+        worst = int(np.argmax(err - tol))
+        assert np.all(err <= tol), "mindist off at row %d: %r vs %r" % (worst, md[worst], d_lab[worst])
+    if sse is not None:
+        ref = oracle.pairwise_sum(d_lab)
+        assert abs(sse - ref) <= DIST_RTOL * abs(ref) + 1e-30, "SSE %r vs %r" % (sse, ref)
+        rep["sse_ref"] = ref
+        rep["sse_rel_err"] = abs(sse - ref) / abs(ref)
+    c = scan["counts"]
+    rep.update(n_sure=int(c[0]), n_amb=int(c[1]))
+    if check_sandwich and n_corrected is not None and bound == "mp":
+        assert c[0] <= n_corrected <= c[0] + c[1], \
+            "corrected %d not in [%d, %d]" % (n_corrected, c[0], c[0] + c[1])
+    return rep

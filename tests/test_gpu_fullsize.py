@@ -1,13 +1,18 @@
 """Parity at the full sizes of the benchmark workloads, in the launch
-configuration bench.py times, on sampled rows the oracle can compute one by
-one."""
+configuration bench.py times, against the oracle over EVERY row.
+
+The oracle's per-row quantities come from one streamed O4 pass over all
+pairs (oracle.mp_scan): labels under the gate, the distance at each returned
+label (mindist within 1e-6 relative), the SSE against the oracle's pairwise
+sum of those distances, near-optimality everywhere, and the corrected-pair
+sandwich over all n * k pairs."""
 
 import numpy as np
 import pytest
 
 import oracle
 import workloads as W
-from tests.gpu_helpers import check_assignment, check_pairwise
+from tests.gpu_helpers import check_assignment, check_assignment_scan, check_pairwise, scan_rows
 
 pytestmark = pytest.mark.gpu
 
@@ -33,51 +38,70 @@ def dist_bench():
     return X, C
 
 
-def test_dist_bench_full_fp16(ctx, dist_bench):
+def test_dist_bench_full_fp16_and_fp64_direct(ctx, dist_bench):
+    """1e6 x 128 against 4096 centres, N(0,1): the mixed FP16 -> FP64 pass
+    (the kernel bench.py times) and the plain FP64 direct kernel, every row
+    checked against the oracle."""
     X, C = dist_bench
+    n, d = X.shape
     p = km.Precision(km.KM_LOW_FP16, km.KM_ALPHA_PAPER_EQ, 5.0)
     Xd = torch.from_numpy(X).cuda()
     Cd = torch.from_numpy(C).cuda()
-    labels, mind, sse, st = km.kmeans_assign(ctx, Xd, Cd, p, mindist=True, sse=True)
-    rows = np.sort(np.random.default_rng(11).choice(len(X), 384, replace=False))
-    rep = check_assignment(X, C, 0, st["alpha_used"], host(labels), host(mind), None, None,
-                           min_coverage=0.99, rows=rows)
-    # corrected-pair sandwich and per-pair values on the sampled rows (same
-    # kernel arithmetic, materialised)
-    D, fl = km.kmeans_pairwise(ctx, Xd[torch.from_numpy(rows).cuda()].contiguous(), Cd, p,
-                               flagged=True)
-    prep = check_pairwise(X[rows], C, 0, st["alpha_used"], host(D), host(fl))
+    lab_m, mind_m, sse_m, st = km.kmeans_assign(ctx, Xd, Cd, p, mindist=True, sse=True)
+    alpha = st["alpha_used"]
+    # the benchmark's own call: labels seeded by an earlier assignment, no
+    # refinement, no statistics -- the labels must be the same, bitwise
+    seed_labels = torch.from_numpy(
+        np.random.default_rng(5).integers(0, C.shape[0], n).astype(np.int32)).cuda()
+    lab_b, _, _, _ = km.kmeans_assign(ctx, Xd, Cd, p, labels=seed_labels.clone(), stats=False,
+                                      labels_hint=True)
+    torch.cuda.synchronize()
+    assert torch.equal(lab_b, lab_m)
+    lab_d, mind_d, _, _ = km.kmeans_assign(ctx, Xd, Cd, km.Precision(km.KM_EXACT64), mindist=True)
+    lab_m, lab_d = host(lab_m), host(lab_d)
+    scan = scan_rows(X, C, 0, alpha, [lab_m, lab_d])
+    rep = check_assignment_scan(scan, 0, lab_m, host(mind_m), float(host(sse_m)[0]),
+                                st["n_corrected"], min_coverage=0.9999)
+    rep64 = check_assignment_scan(scan, 1, lab_d, host(mind_d), None, None, bound="fp64", d=d,
+                                  min_coverage=0.99999)
     eta = st["n_corrected"] / st["n_pairs"]
     assert 0 < eta < 1e-3
-    # SSE equals the sum of the reported FP64 distances (within FP32 rounding)
-    assert float(host(sse)[0]) == pytest.approx(host(mind).astype(np.float64).sum(), rel=1e-6)
-    print("gate coverage %.4f, eta %.3g, max rel err (kept) %.3g"
-          % (rep["coverage"], eta, prep["max_rel_err_kept"]))
+    # per-pair values and flags of a slab of rows, materialised by the same
+    # arithmetic
+    rows = np.arange(4096, 4096 + 384)
+    D, fl = km.kmeans_pairwise(ctx, Xd[4096:4096 + 384].contiguous(), Cd, p, flagged=True)
+    prep = check_pairwise(X[rows], C, 0, alpha, host(D), host(fl))
+    print("FP16: all %d rows, gate coverage %.6f, %d ungated, %d labels differ from O1, "
+          "eta %.3g in [%.3g, %.3g], SSE rel err %.2g; FP64 direct: coverage %.7f, %d differ; "
+          "max rel err (kept, slab) %.3g"
+          % (n, rep["coverage"], rep["n_ungated"], rep["n_diff"], eta,
+             rep["n_sure"] / (n * C.shape[0]), (rep["n_sure"] + rep["n_amb"]) / (n * C.shape[0]),
+             rep["sse_rel_err"], rep64["coverage"], rep64["n_diff"], prep["max_rel_err_kept"]))
 
 
-def test_dist_bench_full_fp64_direct(ctx, dist_bench):
-    X, C = dist_bench
+def test_dist_bench_cancellation_variant_full(ctx):
+    """+1e3 offset, spread 1e-2, at the full 1e6 x 128 against 4096: every
+    pair is surely corrected in FP16 and in BF16 (each coordinate rounds to
+    within a unit of 1000), so both passes give the FP64 direct values
+    rounded to FP32; every row is checked."""
+    X, C = W.cancellation_pair(1_000_000, 4096, 128, seed=1002)
+    n, k = X.shape[0], C.shape[0]
     Xd = torch.from_numpy(X).cuda()
     Cd = torch.from_numpy(C).cuda()
-    labels, mind, _, st = km.kmeans_assign(ctx, Xd, Cd, km.Precision(km.KM_EXACT64), mindist=True)
-    rows = np.sort(np.random.default_rng(12).choice(len(X), 256, replace=False))
-    check_assignment(X, C, None, None, host(labels), host(mind), None, None,
-                     min_coverage=0.999, rows=rows)
-
-
-def test_dist_bench_cancellation_variant(ctx):
-    # +1e3 offset, spread 1e-2: every pair fails the test; smaller n keeps the
-    # fully corrected pass short
-    X, C = W.cancellation_pair(100_000, 4096, 128, seed=1002)
-    Xd = torch.from_numpy(X).cuda()
-    Cd = torch.from_numpy(C).cuda()
-    for low, fmt in ((km.KM_LOW_FP16, 0), (km.KM_LOW_BF16, 1)):
+    out = {}
+    for low in (km.KM_LOW_FP16, km.KM_LOW_BF16):
         p = km.Precision(low, km.KM_ALPHA_PAPER_EQ, 5.0)
-        labels, mind, _, st = km.kmeans_assign(ctx, Xd, Cd, p, mindist=True)
-        assert st["n_corrected"] == st["n_pairs"]
-        rows = np.sort(np.random.default_rng(13).choice(len(X), 128, replace=False))
-        check_assignment(X, C, fmt, st["alpha_used"], host(labels), host(mind), None, None,
-                         min_coverage=0.99, rows=rows)
+        lab, mind, sse, st = km.kmeans_assign(ctx, Xd, Cd, p, mindist=True, sse=True)
+        assert st["n_corrected"] == st["n_pairs"] == n * k
+        out[low] = (host(lab), host(mind), float(host(sse)[0]), st)
+    # both formats correct every pair, so they return the same assignment
+    assert np.array_equal(out[km.KM_LOW_FP16][0], out[km.KM_LOW_BF16][0])
+    lab, mind, sse, st = out[km.KM_LOW_FP16]
+    scan = scan_rows(X, C, 0, st["alpha_used"], [lab])
+    assert scan["counts"][0] == n * k  # all surely corrected (FP16 rounding)
+    rep = check_assignment_scan(scan, 0, lab, mind, sse, st["n_corrected"], min_coverage=0.99)
+    print("cancellation variant: all %d rows, coverage %.6f, %d labels differ from O1"
+          % (n, rep["coverage"], rep["n_diff"]))
 
 
 def test_large_clustering_full_assign(ctx):
@@ -87,11 +111,11 @@ def test_large_clustering_full_assign(ctx):
     C0 = W.init_centroids(X, cfg["k"], cfg["init_seed"])
     Xd = torch.from_numpy(X).cuda()
     rows = np.sort(np.random.default_rng(14).choice(len(X), 512, replace=False))
-    for low, fmt in ((km.KM_LOW_FP16, 0), (km.KM_LOW_BF16, 1), (km.KM_LOW_FP32, 2)):
-        p = km.Precision(low, km.KM_ALPHA_PAPER_EQ, 5.0)
-        labels, mind, _, st = km.kmeans_assign(ctx, Xd, torch.from_numpy(C0).cuda(), p, mindist=True)
-        # at random initial centres several centres share a blob: more near
-        # ties than at convergence, so the gate covers fewer points
-        # (the FP32 bound is the worst case of thm:dist-exp and covers fewer)
-        check_assignment(X, C0, fmt, st["alpha_used"], host(labels), host(mind), None, None,
-                         min_coverage=0.95 if fmt < 2 else 0.85, rows=rows)
+    # FP32 with the threshold: the worst-case FP32 bound of thm:dist-exp
+    # covers fewer points at random initial centres (several centres share a
+    # blob), so it is checked on sampled rows; FP16 and BF16 over all rows
+    # are in the step-locked Lloyd test of the large clustering
+    p = km.Precision(km.KM_LOW_FP32, km.KM_ALPHA_PAPER_EQ, 5.0)
+    labels, mind, _, st = km.kmeans_assign(ctx, Xd, torch.from_numpy(C0).cuda(), p, mindist=True)
+    check_assignment(X, C0, 2, st["alpha_used"], host(labels), host(mind), None, None,
+                     min_coverage=0.85, rows=rows)

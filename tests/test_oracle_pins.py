@@ -485,3 +485,165 @@ def test_hw_alpha_cancellation_all_flagged():
         dh, S = _fp32_expanded(X, C, fmt)
         a = oracle.alpha_value(fmt, 64, 5.0, "hw")
         assert np.all(dh <= a * S)
+
+
+# ---------------------------------------------------------------------------
+# O4's bound A on the FP32 evaluation of the expanded formula
+# ---------------------------------------------------------------------------
+
+def _lib_round(a, fmt):
+    """Rounded inputs from library conversions (numpy float16, torch
+    bfloat16), as float32: independent of the oracle's own rounding."""
+    if fmt == oracle.FP16:
+        return a.astype(np.float16).astype(np.float32)
+    torch = pytest.importorskip("torch")
+    return torch.from_numpy(np.ascontiguousarray(a)).to(torch.bfloat16).float().numpy()
+
+
+def _f32_sum_seq(terms):
+    """Sequential float32 sum over the last axis (one rounding per add)."""
+    acc = np.zeros(terms.shape[:-1], dtype=np.float32)
+    for l in range(terms.shape[-1]):
+        acc = (acc + terms[..., l]).astype(np.float32)
+    return acc
+
+
+def _f32_sum_pairwise(terms):
+    t = terms.astype(np.float32)
+    while t.shape[-1] > 1:
+        if t.shape[-1] % 2:
+            t = np.concatenate([t, np.zeros(t.shape[:-1] + (1,), np.float32)], axis=-1)
+        t = (t[..., 0::2] + t[..., 1::2]).astype(np.float32)
+    return t[..., 0]
+
+
+def _f32_sum_blocked(terms, width, init=None):
+    """Blocks of `width` consecutive terms summed exactly (FP64 holds the sum
+    of a few products of 11- or 8-bit significands without loss at these
+    magnitudes) and rounded once, then accumulated in float32 -- the shape of
+    a matrix-core K step."""
+    acc = np.zeros(terms.shape[:-1], dtype=np.float32) if init is None else init.astype(np.float32)
+    for s in range(0, terms.shape[-1], width):
+        blk = terms[..., s:s + width].astype(np.float64).sum(axis=-1).astype(np.float32)
+        acc = (acc + blk).astype(np.float32)
+    return acc
+
+
+def _expanded_fp32_variants(Xq, Cq):
+    """d^ = max(||x~||^2 + ||c~||^2 - 2 x~^T c~, 0) in float32 under several
+    summation orders, including the accumulator form W = -||c~||^2/2 +
+    x~^T c~, d^ = ||x~||^2 - 2W.  Products of FP16/BF16 values are exact in
+    float32.  Returns a list of (name, (m, k) float64 arrays)."""
+    prod = Xq[:, None, :] * Cq[None, :, :]  # exact float32 products
+    sqx = Xq * Xq
+    sqc = Cq * Cq
+    out = []
+    for name, red in (("sequential", _f32_sum_seq), ("pairwise", _f32_sum_pairwise),
+                      ("blocked16", lambda t: _f32_sum_blocked(t, 16)),
+                      ("blocked8", lambda t: _f32_sum_blocked(t, 8)),
+                      ("reversed", lambda t: _f32_sum_seq(t[..., ::-1]))):
+        nx = red(sqx)[:, None]
+        nc = red(sqc)[None, :]
+        dot = red(prod)
+        dh = ((nx + nc).astype(np.float32) - (np.float32(2) * dot).astype(np.float32)).astype(np.float32)
+        out.append((name, np.maximum(dh, np.float32(0)).astype(np.float64)))
+    # accumulator form: start at -||c~||^2/2, add the K steps, d^ = nx - 2W
+    nx = _f32_sum_blocked(sqx, 8)[:, None]
+    nc = _f32_sum_seq(sqc)[None, :]
+    W = _f32_sum_blocked(prod, 16, init=np.broadcast_to(-np.float32(0.5) * nc, prod.shape[:2]))
+    dh = (nx - (np.float32(2) * W).astype(np.float32)).astype(np.float32)
+    out.append(("accumulator", np.maximum(dh, np.float32(0)).astype(np.float64)))
+    return out
+
+
+def _aligned_rows(rows, d, g, p=7):
+    # p = 7 fraction bits: representable in BF16 and FP16 alike
+    v = np.empty((rows, d), dtype=np.float32)
+    v[:, 0] = 2048.0
+    v[:, 1:] = 0.5 * (1.0 + 2.0 ** -p) * np.where(g.random((rows, d - 1)) < 0.5, -1.0, 1.0)
+    return v
+
+
+def _a_cases(d, seed):
+    g = np.random.default_rng(seed)
+    m, k = 48, 64
+    yield "normal", (g.standard_normal((m, d)).astype(np.float32),
+                     g.standard_normal((k, d)).astype(np.float32))
+    yield "cancellation", ((1e3 + 1e-2 * g.standard_normal((m, d))).astype(np.float32),
+                           (1e3 + 1e-2 * g.standard_normal((k, d))).astype(np.float32))
+    # every coordinate positive and of similar size: rounding errors of the
+    # sums share a sign, and x~^T c~ is close to its bound ||x~|| ||c~||
+    yield "sign_aligned", (g.uniform(0.5, 1.5, (m, d)).astype(np.float32),
+                           g.uniform(0.5, 1.5, (k, d)).astype(np.float32))
+    # mixed magnitudes: large and tiny coordinates in one row
+    scale = 10.0 ** g.integers(-3, 3, size=d)
+    yield "mixed_scale", ((g.standard_normal((m, d)) * scale).astype(np.float32),
+                          (g.standard_normal((k, d)) * scale).astype(np.float32))
+    # rounding-aligned sums: a leading coordinate 2048 (square 2^22, FP32
+    # spacing 1/2 there) followed by coordinates +-(1/2)(1 + 2^-p), whose
+    # squares exceed a quarter by a little, so that every addition of a
+    # sequential FP32 sum of squares rounds up by almost half a spacing
+    yield "rounding_aligned", (_aligned_rows(m, d, g), _aligned_rows(k, d, g))
+
+
+@pytest.mark.parametrize("fmt", [oracle.FP16, oracle.BF16])
+@pytest.mark.parametrize("d", [5, 64, 128])
+def test_mp_bound_A_covers_fp32_evaluations(fmt, d):
+    # Theorem thm:dist-exp applied to the rounded inputs with FP32
+    # arithmetic: every FP32 evaluation of the expanded formula of x~, c~
+    # lies within A = gamma'_{d+4}(S + 2|x~|^T|c~|) of q = d(x~, c~)^2,
+    # whatever the summation order.  The evaluations here are written
+    # independently of the oracle (library rounding, numpy float32).
+    worst = 0.0
+    for case, (X, C) in _a_cases(d, 700 + 10 * d + fmt):
+        if fmt == oracle.FP16 and case == "mixed_scale":
+            X = np.clip(X, -6e4, 6e4)
+            C = np.clip(C, -6e4, 6e4)
+        r = oracle.mp_rows(X, C, fmt, 0.5)
+        assert r["n_bad"] == 0
+        Xq, Cq = _lib_round(X, fmt), _lib_round(C, fmt)
+        P = np.abs(Xq.astype(np.float64)) @ np.abs(Cq.astype(np.float64)).T
+        for name, dh in _expanded_fp32_variants(Xq, Cq):
+            err = np.abs(dh - r["q"])
+            assert np.all(err <= r["A"]), "%s/%s: FP32 error %.3g exceeds A %.3g" % (
+                case, name, err.max(), r["A"].flat[np.argmax(err - r["A"])])
+            worst = max(worst, float((err / r["A"]).max()))
+            # a planted slip: A built on the FP64 unit roundoff instead of
+            # twice the FP32 one is far too small for any FP32 evaluation
+            A_slip = oracle.gamma(d + 4, oracle.unit_roundoff(3)) * (r["S"] + 2 * P)
+            if np.any(err > 0):
+                assert np.any(err > A_slip), "%s/%s: slip not detected" % (case, name)
+            if case == "rounding_aligned" and name == "sequential" and d >= 64:
+                # another planted slip: the length of the sum dropped from
+                # the bound (gamma'_4 instead of gamma'_{d+4})
+                A_short = oracle.gamma(4, 2 * oracle.unit_roundoff(2)) * (r["S"] + 2 * P)
+                assert np.any(err > A_short), "dropped dimension not detected"
+    # the bound is not vacuous: some evaluation uses a visible part of it
+    assert worst > 1e-4, "largest error only %.3g of A" % worst
+
+
+@pytest.mark.parametrize("fmt", [oracle.FP16, oracle.BF16])
+def test_mp_classes_bracket_fp32_test_decisions(fmt):
+    # the band of O4's classes covers the FP32 evaluation of the test in the
+    # accumulator form (flag iff W + alpha nc/2 >= (1 - alpha) nx / 2): a
+    # surely corrected pair is flagged and a surely kept one is not, for
+    # every summation order of the cross term
+    d = 32
+    X, C = _boundary_pairs(d, 90 + fmt)
+    a = np.float32(0.25)
+    r = oracle.mp_rows(X, C, fmt, float(a))
+    Xq, Cq = _lib_round(X, fmt), _lib_round(C, fmt)
+    prod = Xq[:, None, :] * Cq[None, :, :]
+    nx = _f32_sum_blocked(Xq * Xq, 8)
+    nc = _f32_sum_seq(Cq * Cq)
+    hx = (np.float32(0.5) * ((np.float32(1) - a) * nx).astype(np.float32)).astype(np.float32)
+    ca = (a * (np.float32(0.5) * nc).astype(np.float32)).astype(np.float32)
+    init = np.broadcast_to(-(np.float32(0.5) * nc), prod.shape[:2])
+    for W in (_f32_sum_blocked(prod, 16, init=init),
+              (init + _f32_sum_seq(prod)).astype(np.float32)):
+        flag = (W + ca[None, :]).astype(np.float32) >= hx[:, None]
+        assert np.all(flag[r["cls"] == -1])
+        assert not np.any(flag[r["cls"] == 1])
+    # both classes occur, and the ambiguous band is a small minority
+    assert (r["cls"] == -1).any() and (r["cls"] == 1).any()
+    assert (r["cls"] == 0).mean() < 0.05
