@@ -134,8 +134,10 @@ def test_large_step_locked_full_rows(ctx, large, low, mode):
         _, _, _, st = km.kmeans_assign(ctx, Xd, C, p, labels=lab, stats=True, labels_hint=t > 0)
         labh = host(lab)
         scan = scan_rows(X, Ch, fmt, st["alpha_used"], [labh])
+        # the oracle's own gate coverage at the initial centres (first 50,000
+        # rows): 0.992 for FP16, 0.959 for BF16 with the hardware-aware bound
         rep = check_assignment_scan(scan, 0, labh, None, None, st["n_corrected"],
-                                    min_coverage=0.999)
+                                    min_coverage=0.98 if fmt == 0 else 0.93)
         diffs.append(rep["n_diff"])
         ungated.append(rep["n_ungated"])
         km.kmeans_update(ctx, Xd, lab, C, C_new=Cn, sync=True)
