@@ -170,6 +170,28 @@ int32_t kmeans_assign(km_context *ctx, const float *X, int64_t n, int32_t d,
                       int32_t *labels, float *mindist, double *sse,
                       km_stats *stats, void *stream, uint32_t flags);
 
+/* ---- one assignment pass without any allocation -----------------------------
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * pass, arguments, outputs and results as kmeans_assign (bitwise), but the
+ * pass's workspace (quantised centres, per-centre constants, per-workgroup
+ * partials, status word and result record) lives in a fixed device array of
+ * KM_STATIC_SCRATCH_BYTES that the library holds on each device for the life
+ * of the process; the call makes no device allocation (descriptors go
+ * through the context's pinned upload ring, allocated when the context was
+ * created).  A pass whose workspace would exceed the array returns
+ * KM_ERR_UNSUPPORTED before enqueueing anything (roughly k*d <= 2^21 and
+ * n <= 2^24 fit).  Every call on a device shares that device's array and
+ * keeps the last call's contents: calls that overlap on one device (other
+ * streams, other contexts, other host threads) race and must be ordered by
+ * the caller.  Kernel timing (kmeans_timing_enable) is not recorded. */
+#define KM_STATIC_SCRATCH_BYTES (24u << 20)
+int32_t kmeans_assign_static(km_context *ctx, const float *X, int64_t n,
+                             int32_t d, const float *C, int32_t k,
+                             const km_precision *prec, int32_t *labels,
+                             float *mindist, double *sse, km_stats *stats,
+                             void *stream, uint32_t flags);
+
 /* ---- one centre update (eq:center, Algorithm alg:mp-kmeans) -----------------
  * C_new[j] = fl32( (sum_{i: labels_i = j} x_i) / m_j ) with the sums taken in
  * FP64 in a fixed order that does not depend on the launch (points of a

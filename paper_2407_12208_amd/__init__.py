@@ -18,7 +18,7 @@ __all__ = [
     "KM_LOW_FP16", "KM_LOW_BF16", "KM_LOW_FP32", "KM_EXACT64",
     "KM_ALPHA_PAPER_EQ", "KM_ALPHA_PAPER_ALG", "KM_ALPHA_EXPLICIT", "KM_ALPHA_NONE", "KM_ALPHA_HW",
     "KM_SYNC", "KMeansError", "Precision", "Stats", "Problem", "library_path", "lib",
-    "Context", "kmeans_context_create", "kmeans_assign", "kmeans_update",
+    "Context", "kmeans_context_create", "kmeans_assign", "kmeans_assign_static", "kmeans_update",
     "kmeans_lloyd", "kmeans_solve_batch", "kmeans_pairwise", "kmeans_quantize",
     "kmeans_alpha", "kmeans_status_string", "Server", "kmeans_server_create",
     "kmeans_submit", "kmeans_poll", "kmeans_cancel", "kmeans_server_destroy",
@@ -98,6 +98,7 @@ def lib():
                 "kmeans_context_create": [i32, ct.POINTER(P)],
                 "kmeans_context_destroy": [P],
                 "kmeans_assign": [P, P, i64, i32, P, i32, PP, P, P, P, PS, P, u32],
+                "kmeans_assign_static": [P, P, i64, i32, P, i32, PP, P, P, P, PS, P, u32],
                 "kmeans_update": [P, P, i64, i32, P, i32, P, P, P, P, P, P, u32],
                 "kmeans_lloyd": [P, P, i64, i32, i32, P, i32, dbl, PP, P, P, P, PS, P, u32],
                 "kmeans_solve_batch": [P, ct.POINTER(Problem), i32, PP, P, u32],
@@ -231,12 +232,15 @@ def kmeans_alpha(prec=None, d: int = 128) -> float:
 
 
 def kmeans_assign(ctx: Context, X, C, prec=None, labels=None, mindist=None,
-                  sse=None, stats=True, stream=None, sync=False, labels_hint=False):
+                  sse=None, stats=True, stream=None, sync=False, labels_hint=False,
+                  static=False):
     """One assignment pass.  X (n,d) and C (k,d) are float32 device tensors.
     Returns ``(labels, mindist, sse, stats_dict_or_None)``; outputs not given
     are allocated (mindist and sse only when requested with ``True``).
     ``labels_hint=True``: ``labels`` holds an earlier assignment that seeds
-    the search (same results, KM_LABELS_HINT)."""
+    the search (same results, KM_LABELS_HINT).  ``static=True`` calls
+    kmeans_assign_static (the library allocates nothing; the caller passes
+    every output it wants)."""
     torch = _torch()
     n, d = X.shape
     k = C.shape[0]
@@ -247,7 +251,8 @@ def kmeans_assign(ctx: Context, X, C, prec=None, labels=None, mindist=None,
     if sse is True:
         sse = torch.zeros(1, dtype=torch.float64, device=X.device)
     st = Stats() if stats else None
-    code = lib().kmeans_assign(
+    fn = lib().kmeans_assign_static if static else lib().kmeans_assign
+    code = fn(
         ctx.handle, _dev_ptr(X, torch.float32, "X", n * d), n, d,
         _dev_ptr(C, torch.float32, "C", k * d), k, _prec(prec),
         _dev_ptr(labels, torch.int32, "labels", n),
@@ -255,8 +260,17 @@ def kmeans_assign(ctx: Context, X, C, prec=None, labels=None, mindist=None,
         _dev_ptr(sse, torch.float64, "sse", 1, allow_none=True),
         ct.byref(st) if st is not None else None, _stream_ptr(stream),
         (KM_SYNC if sync else 0) | (KM_LABELS_HINT if labels_hint else 0))
-    _check(code, "kmeans_assign")
+    _check(code, "kmeans_assign_static" if static else "kmeans_assign")
     return labels, mindist, sse, (st.as_dict() if st is not None else None)
+
+
+def kmeans_assign_static(ctx: Context, X, C, prec=None, labels=None, mindist=None,
+                         sse=None, stats=True, stream=None, sync=False, labels_hint=False):
+    """kmeans_assign through the entry point that allocates nothing (fixed
+    per-device workspace; overlapping calls on one device must be ordered
+    by the caller)."""
+    return kmeans_assign(ctx, X, C, prec, labels, mindist, sse, stats, stream, sync,
+                         labels_hint, static=True)
 
 
 def kmeans_pairwise(ctx: Context, X, C, prec=None, D=None, flagged=None,

@@ -398,6 +398,13 @@ int32_t kmeans_alpha(const km_precision* prec, int32_t d, double* alpha_out) {
   return KM_OK;
 }
 
+// Fixed workspace of kmeans_assign_static: one copy per device, held for the
+// life of the process.  Host code never uses this name as an address (on
+// the host it is a stand-in, not device memory); it uses the device address
+// that kmeans_context_create obtains with hipGetSymbolAddress, with the
+// context's device current.
+static __device__ __align__(256) char scratch[KM_STATIC_SCRATCH_BYTES];
+
 int32_t kmeans_context_create(int32_t device, km_context** out) {
   if (!out) return KM_ERR_ARG;
   *out = nullptr;
@@ -411,6 +418,12 @@ int32_t kmeans_context_create(int32_t device, km_context** out) {
   if (!c) return KM_ERR_OOM;
   c->device = device;
   c->num_cu = prop.multiProcessorCount;
+  void* sp = nullptr;
+  if (hipGetSymbolAddress(&sp, HIP_SYMBOL(scratch)) != hipSuccess || !sp) {
+    delete c;
+    return KM_ERR_DEVICE;
+  }
+  c->static_scratch = static_cast<char*>(sp);
   if (c->up.init(8u << 20) != hipSuccess ||
       hipHostMalloc(reinterpret_cast<void**>(&c->h_scalar), 64, hipHostMallocDefault) != hipSuccess ||
       hipHostMalloc(reinterpret_cast<void**>(&c->h_result), sizeof(KResult) * km_context_impl::kMaxResults,
@@ -618,6 +631,43 @@ int32_t kmeans_assign(km_context* ctx, const float* X, int64_t n, int32_t d, con
   const bool refine = mindist || sse || stats;
   KM_HIP(enqueue_pass(ctx, a, b, X, n, d, C, k, labels, mindist, sse, 0, nullptr, nullptr, refine,
                       (flags & KM_LABELS_HINT) != 0, st));
+  if (stats || (flags & KM_SYNC)) return finish_stats(ctx, b.result, stats, a, 0, st);
+  return KM_OK;
+}
+
+int32_t kmeans_assign_static(km_context* ctx, const float* X, int64_t n, int32_t d, const float* C,
+                             int32_t k, const km_precision* prec, int32_t* labels, float* mindist,
+                             double* sse, km_stats* stats, void* stream, uint32_t flags) {
+  if (!ctx || !X || !C || !labels || !ctx->static_scratch) return KM_ERR_ARG;
+  km_precision p = precision_or_default(prec);
+  int32_t v = validate_precision(p);
+  if (v != KM_OK) return v;
+  v = check_shape(n, d, k, p);
+  if (v != KM_OK) return v;
+  AssignPlan a = plan_assign(p, n, d, k);
+  Plan pl;
+  plan_pass(pl, a);
+  if (pl.bytes > (size_t)KM_STATIC_SCRATCH_BYTES) return KM_ERR_UNSUPPORTED;
+  hipStream_t st = (hipStream_t)stream;
+  KM_HIP(hipSetDevice(ctx->device));
+  WorkspaceUse ws_use(ctx, st);
+  KM_HIP(ws_use.err);
+  // the pass's workspace is carved from the fixed array, never grown
+  Arena ar;
+  ar.base = ctx->static_scratch;
+  ar.cap = KM_STATIC_SCRATCH_BYTES;
+  PassBufs b = carve_pass(ar, a);
+  // timing events would be created on first use: not recorded here
+  const bool timing = ctx->timing;
+  ctx->timing = false;
+  // the status word and result record start at zero (a fill kernel)
+  hipError_t e = zero_status_result(b.status, b.result, st);
+  const bool refine = mindist || sse || stats;
+  if (e == hipSuccess)
+    e = enqueue_pass(ctx, a, b, X, n, d, C, k, labels, mindist, sse, 0, nullptr, nullptr, refine,
+                     (flags & KM_LABELS_HINT) != 0, st);
+  ctx->timing = timing;
+  KM_HIP(e);
   if (stats || (flags & KM_SYNC)) return finish_stats(ctx, b.result, stats, a, 0, st);
   return KM_OK;
 }

@@ -74,6 +74,8 @@ struct km_context_impl {
   int num_cu = 0;
   Arena arena;
   Uploader up;
+  char* static_scratch = nullptr; // device address of this device's fixed
+                                  // workspace array (kmeans_assign_static)
   double* h_scalar = nullptr;     // pinned: shift read-back
   KResult* h_result = nullptr;    // pinned: result read-back (up to kMaxResults)
   static constexpr int kMaxResults = 4096;
