@@ -299,6 +299,15 @@ hipError_t read_results(km_context_impl* ctx, const std::vector<const KResult*>&
 }
 
 void plan_update(Plan& pl, int64_t n, int d, int k) {
+  const OwnShape sh = own_shape(d, k);
+  if (sh.owners > 0) {
+    const int64_t nch = (n + own_chunk(sh) - 1) / own_chunk(sh);
+    pl.add<double>((size_t)nch * k * d);  // chunk partials
+    pl.add<int32_t>((size_t)nch * k);     // chunk counts
+    pl.add<double>((size_t)nch);          // chunk SSE partials
+    pl.add<double>((size_t)k);            // shift2
+    return;
+  }
   const int ntiles = (int)((n + kUpdTile - 1) / kUpdTile);
   pl.add<int32_t>((size_t)k * ntiles);  // hist
   pl.add<int32_t>((size_t)k * ntiles);  // offs
@@ -312,6 +321,22 @@ void plan_update(Plan& pl, int64_t n, int d, int k) {
 
 UpdateProb carve_update(Arena& a, int64_t n, int d, int k) {
   UpdateProb u{};
+  const OwnShape sh = own_shape(d, k);
+  if (sh.owners > 0) {
+    const int64_t nch = (n + own_chunk(sh) - 1) / own_chunk(sh);
+    u.pacc = a.take<double>((size_t)nch * k * d);
+    u.pcnt = a.take<int32_t>((size_t)nch * k);
+    u.psse = a.take<double>((size_t)nch);
+    u.shift2 = a.take<double>((size_t)k);
+    u.owners = sh.owners;
+    u.lp = sh.lp;
+    u.nc = sh.nc;
+    u.nchunk = (int)nch;
+    u.n = n;
+    u.d = d;
+    u.k = k;
+    return u;
+  }
   const int ntiles = (int)((n + kUpdTile - 1) / kUpdTile);
   u.hist = a.take<int32_t>((size_t)k * ntiles);
   u.offs = a.take<int32_t>((size_t)k * ntiles);
@@ -330,7 +355,69 @@ UpdateProb carve_update(Arena& a, int64_t n, int d, int k) {
   return u;
 }
 
+hipError_t run_update_sort(km_context_impl* ctx, const std::vector<UpdateProb>& probs, hipStream_t st);
+
+// Owner-path problems: part launches grouped by coordinates per lane, SSE
+// request and the workgroups per compute unit their LDS allows (a launch
+// sizes its LDS for its largest problem), then one finalize and one shift
+// launch over all of them.  The grouping never changes a problem's result.
+static hipError_t run_update_own(km_context_impl* ctx, const std::vector<UpdateProb>& probs, hipStream_t st) {
+  constexpr int kLdsPerCu = 160 * 1024;
+  constexpr int kFit = 3;  // 1, 2, 3 or more workgroups per compute unit
+  std::vector<UpdateProb> grp[2][2][kFit];
+  for (const UpdateProb& u : probs) {
+    const bool sse = u.sse_out != nullptr;
+    const int need = kOwnWaves * own_wave_bytes(u.owners, u.d, u.k) + (sse ? 4 * u.k * u.d : 0);
+    const int fit = std::min(kFit, std::max(1, kLdsPerCu / need));
+    grp[u.nc - 1][sse][fit - 1].push_back(u);
+  }
+  std::vector<UpdateProb> all;
+  std::vector<std::pair<size_t, size_t>> ranges;  // (first, count) per part launch
+  for (auto& a : grp)
+    for (auto& b : a)
+      for (auto& g : b)
+        if (!g.empty()) {
+          ranges.emplace_back(all.size(), g.size());
+          all.insert(all.end(), g.begin(), g.end());
+        }
+  const int np = (int)all.size();
+  std::vector<int> fin(np);
+  for (int i = 0; i < np; ++i) {
+    const int J = own_fin_clusters(all[i].d);
+    fin[i] = (all[i].k + J - 1) / J;
+  }
+  Pack pk;
+  const size_t op = pk.add(all.data(), all.size() * sizeof(UpdateProb));
+  std::vector<size_t> oc;
+  for (auto& r : ranges) {
+    std::vector<int> ch(r.second);
+    for (size_t i = 0; i < r.second; ++i) ch[i] = all[r.first + i].nchunk;
+    std::vector<int32_t> pre = prefix(ch);
+    oc.push_back(pk.add(pre.data(), pre.size() * sizeof(int32_t)));
+  }
+  std::vector<int32_t> pf = prefix(fin);
+  const size_t of = pk.add(pf.data(), pf.size() * sizeof(int32_t));
+  char* d = pk.upload(ctx, st);
+  if (!d) return hipErrorOutOfMemory;
+  const UpdateProb* dprobs = (const UpdateProb*)(d + op);
+  hipError_t e = hipSuccess;
+  for (size_t g = 0; g < ranges.size() && e == hipSuccess; ++g)
+    e = launch_update_own_part(dprobs + ranges[g].first, all.data() + ranges[g].first, (int)ranges[g].second,
+                               (const int32_t*)(d + oc[g]), st);
+  if (e == hipSuccess) e = launch_update_own_fin(dprobs, all.data(), np, (const int32_t*)(d + of), st);
+  return e;
+}
+
 hipError_t run_update(km_context_impl* ctx, const std::vector<UpdateProb>& probs, hipStream_t st) {
+  std::vector<UpdateProb> sorted, own;
+  for (const UpdateProb& u : probs) (u.owners > 0 ? own : sorted).push_back(u);
+  hipError_t e = hipSuccess;
+  if (!sorted.empty()) e = run_update_sort(ctx, sorted, st);
+  if (e == hipSuccess && !own.empty()) e = run_update_own(ctx, own, st);
+  return e;
+}
+
+hipError_t run_update_sort(km_context_impl* ctx, const std::vector<UpdateProb>& probs, hipStream_t st) {
   const int np = (int)probs.size();
   std::vector<int> tiles(np), cl(np), chunkwg(np), clwg(np), scatwg(np);
   for (int i = 0; i < np; ++i) {

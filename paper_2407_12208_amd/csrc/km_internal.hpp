@@ -122,6 +122,11 @@ struct UpdateProb {
   int64_t n;
   int d, k, ntiles;
   int chunk;               // members per partial sum (upd_chunk(d))
+  // owner path (owners > 0, small k*d): per-chunk FP64 partials
+  double* pacc;            // nchunk * k * d
+  int32_t* pcnt;           // nchunk * k
+  double* psse;            // nchunk
+  int owners, lp, nc, nchunk;
 };
 
 hipError_t launch_prep(int low, const PrepProb* dprobs, const int32_t* dstart, int nprob, int nwg,
@@ -145,5 +150,42 @@ constexpr int kUpdChunk = 64;    // members per partial sum (the smallest; works
 constexpr int upd_chunk(int d) { return d <= 16 ? 8 * kUpdChunk : kUpdChunk; }
 hipError_t launch_update(const UpdateProb* dprobs, const UpdateProb* hprobs, int nprob,
                          const int32_t* dscratch_i32, hipStream_t st);
+
+// Owner path of the centre update, for small k*d: a wave's lanes are split
+// into `owners` groups of `lp` lanes; each group takes every owners-th point
+// of the wave's run and adds its row into its own FP64 accumulators of all k
+// clusters in LDS (one lane per coordinate, `nc` coordinates per lane), so
+// each accumulator has a single writer and a fixed order.
+constexpr int kOwnWaves = 4;            // waves per workgroup
+constexpr int kOwnIters = 256;          // points per owner per chunk
+constexpr int kOwnWaveBytes = 34816;    // LDS per wave: accumulators + counts
+constexpr int kOwnCentreFloats = 4096;  // LDS staging of C_old (k*d floats)
+struct OwnShape {
+  int owners, lp, nc;
+};
+inline OwnShape own_shape(int d, int k) {
+  OwnShape s{0, 0, 0};
+  if (d < 1 || d > 128 || k < 1 || (int64_t)k * d > kOwnCentreFloats) return s;
+  s.nc = (d + 63) / 64;
+  s.lp = (d + s.nc - 1) / s.nc;
+  const int64_t per_owner = (int64_t)k * d * 8 + (int64_t)k * 4;
+  const int64_t fit = kOwnWaveBytes / per_owner;
+  const int lanes = 64 / s.lp;
+  s.owners = (int)(fit < lanes ? fit : lanes);
+  if (s.owners < 1) s = OwnShape{0, 0, 0};
+  return s;
+}
+// LDS of one wave's accumulators and counts (16-byte multiple)
+inline int own_wave_bytes(int owners, int d, int k) {
+  return (int)((((int64_t)owners * ((int64_t)k * d * 8 + (int64_t)k * 4)) + 15) / 16 * 16);
+}
+// points per chunk (one workgroup)
+inline int64_t own_chunk(const OwnShape& s) { return (int64_t)kOwnWaves * s.owners * kOwnIters; }
+// clusters per finalize workgroup
+constexpr int own_fin_clusters(int d) { return d >= 256 ? 1 : 256 / d; }
+hipError_t launch_update_own_part(const UpdateProb* dprobs, const UpdateProb* hprobs, int nprob,
+                                  const int32_t* dpre, hipStream_t st);
+hipError_t launch_update_own_fin(const UpdateProb* dprobs, const UpdateProb* hprobs, int nprob,
+                                 const int32_t* dpre, hipStream_t st);
 
 }  // namespace km

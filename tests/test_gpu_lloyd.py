@@ -48,7 +48,15 @@ def assert_within_ulps(a, b, ulps=1):
 # ---------------------------------------------------------------------------
 
 @pytest.mark.parametrize("n,d,k", [(5000, 16, 40), (70001, 5, 64), (3000, 128, 300),
-                                   (1, 3, 1), (1025, 7, 1), (300, 200, 512)])
+                                   (1, 3, 1), (1025, 7, 1), (300, 200, 512),
+                                   # small k*d (per-owner LDS accumulators): two
+                                   # coordinates per lane, an odd d, the largest
+                                   # k*d, many owners, whole chunks only, and a
+                                   # million rows
+                                   (40_001, 128, 16), (49_153, 99, 20), (24_577, 64, 64),
+                                   (100_003, 3, 512), (36_864, 5, 64), (1_000_003, 5, 17),
+                                   # just past the owner path's limit
+                                   (20_000, 64, 65)])
 def test_update_matches_oracle(ctx, n, d, k):
     g = np.random.default_rng(n + d + k)
     X = (g.standard_normal((n, d)) * 3 + 1).astype(np.float32)
