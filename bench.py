@@ -192,6 +192,12 @@ def dist_variants(km, ctx, torch, W, np, X, C, Xh, Ch):
                 ("fp16_uniform", P(km.KM_LOW_FP16, km.KM_ALPHA_NONE)),
                 ("bf16_uniform", P(km.KM_LOW_BF16, km.KM_ALPHA_NONE)),
                 ("fp32_uniform", P(km.KM_LOW_FP32, km.KM_ALPHA_NONE)),
+                # other fallback precisions (uniform rule and FP32 correction)
+                ("fp16_fp32", P(km.KM_LOW_FP16, high=km.KM_HIGH_FP32)),
+                ("bf16_fp32", P(km.KM_LOW_BF16, high=km.KM_HIGH_FP32)),
+                ("fp16_fp16", P(km.KM_LOW_FP16, high=km.KM_HIGH_LOW)),
+                ("bf16_bf16", P(km.KM_LOW_BF16, high=km.KM_HIGH_LOW)),
+                ("fp32_fp32", P(km.KM_LOW_FP32, high=km.KM_HIGH_LOW)),
                 ("fp64_direct", P(km.KM_EXACT64)))
     out = {"normal": variant_table(km, ctx, torch, np, X, C, Xh, Ch, variants)}
     cfg = W.DIST_BENCH
@@ -200,7 +206,9 @@ def dist_variants(km, ctx, torch, W, np, X, C, Xh, Ch):
     Xcd = torch.from_numpy(Xc).cuda()
     Ccd = torch.from_numpy(Cc).cuda()
     cvariants = tuple(v for v in variants if v[0] in ("fp16_fp64", "bf16_fp64", "fp16_uniform",
-                                                      "bf16_uniform", "fp32_uniform", "fp64_direct"))
+                                                      "bf16_uniform", "fp32_uniform", "fp16_fp32",
+                                                      "bf16_fp32", "fp16_fp16", "bf16_bf16",
+                                                      "fp32_fp32", "fp64_direct"))
     out["cancellation"] = variant_table(km, ctx, torch, np, Xcd, Ccd, Xc, Cc, cvariants)
     del Xcd, Ccd
     return out
@@ -419,7 +427,9 @@ def main():
         extra["speedup_assign_vs_fp64_direct"] = ms64 / kern_avg_ms
         extra["fp64_direct_frac_of_fp64_peak"] = (3.0 * n * k * d / (ms64 * 1e-3) / 1e12) / FP64_PEAK_TFLOPS
         if not args.no_variants:
-            extra["distance_variants"] = dist_variants(km, ctx, torch, W, np, X, Ca, Xh, Ch)
+            # the timed rounds moved Ca: the variants use the generated centres
+            extra["distance_variants"] = dist_variants(km, ctx, torch, W, np, X,
+                                                       torch.from_numpy(Ch).cuda(), Xh, Ch)
         # single Lloyd solve: 20,000 x 32, 16 blobs, 20 rounds + final pass
         cs = W.LLOYD_SMALL
         Xs, _, _ = W.blobs(cs["n"], cs["d"], cs["k"], cs["seed"])

@@ -94,14 +94,31 @@ enum {
 };
 /* If (d+2) u_l >= 1 gamma is undefined and every pair is corrected. */
 
+/* Precision u of the direct formula that replaces a flagged pair (the
+ * fallback of eq:fallback-rule-mp; Section 6.1 tests the variants).  Every
+ * operation is one correctly rounded operation of that format, differences
+ * first, then one fused multiply-add per coordinate in index order.  The
+ * refinement of the chosen label (mindist, SSE) stays FP64 in every mode. */
+enum {
+  KM_HIGH_FP64 = 0, /* FP64 on the FP32 inputs (default)                    */
+  KM_HIGH_FP32 = 1, /* FP32 on the FP32 inputs: FP16/BF16 -> FP32           */
+  KM_HIGH_LOW = 2   /* the low format itself on the quantised inputs x~, c~:
+                       the uniform rule eq:fallback-rule (FP16 -> FP16,
+                       BF16 -> BF16, FP32 -> FP32)                          */
+};
+
 typedef struct km_precision {
   int32_t low;        /* KM_LOW_* or KM_EXACT64                              */
   int32_t alpha_mode; /* KM_ALPHA_*                                          */
   double rho;         /* safety factor rho~ (> 2 in the paper modes; 5 by
                          default, Section 6.1)                              */
   double alpha;       /* used with KM_ALPHA_EXPLICIT only                   */
+  int32_t high;       /* KM_HIGH_*; KM_EXACT64 takes KM_HIGH_FP64 only       */
+  int32_t reserved;   /* zero                                                */
 } km_precision;
-/* A NULL km_precision* means {KM_LOW_FP16, KM_ALPHA_PAPER_EQ, 5.0, 0}. */
+/* A NULL km_precision* means {KM_LOW_FP16, KM_ALPHA_PAPER_EQ, 5.0, 0,
+ * KM_HIGH_FP64, 0}.  A pass whose threshold flags every pair runs the direct
+ * formula in the correction precision for every pair. */
 
 typedef struct km_stats {
   int64_t n_corrected; /* pairs recomputed by the FP64 direct formula; the

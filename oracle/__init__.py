@@ -68,6 +68,16 @@ def lib():
             L.oracle_round_low.argtypes = [ct.c_float, i32]
             L.oracle_quantize.restype = None
             L.oracle_quantize.argtypes = [P, i64, i32, P]
+            L.oracle_round_exact.restype = dbl
+            L.oracle_round_exact.argtypes = [dbl, dbl, i32]
+            L.oracle_low_sub.restype = dbl
+            L.oracle_low_sub.argtypes = [dbl, dbl, i32]
+            L.oracle_low_fma.restype = dbl
+            L.oracle_low_fma.argtypes = [dbl, dbl, dbl, i32]
+            L.oracle_corr_dist.restype = dbl
+            L.oracle_corr_dist.argtypes = [P, P, i32, i32, i32]
+            L.oracle_corr_rows.restype = None
+            L.oracle_corr_rows.argtypes = [P, i64, i32, P, i32, i32, i32, P]
             L.oracle_sqdist.restype = dbl
             L.oracle_sqdist.argtypes = [P, P, i32]
             L.oracle_pairwise_sum.restype = dbl
@@ -273,6 +283,35 @@ def mp_rows(X, C, fmt: int, alpha: float):
                                 _ptr(out["B"]), _ptr(cls))
     out["cls"] = cls
     out["n_bad"] = int(nbad)
+    return out
+
+
+def low_sub(a: float, b: float, fmt: int) -> float:
+    """O5: a - b rounded once to format fmt (0 FP16, 1 BF16, 2 FP32); a and b
+    must be values of that format."""
+    return lib().oracle_low_sub(float(a), float(b), int(fmt))
+
+
+def low_fma(a: float, b: float, c: float, fmt: int) -> float:
+    """O5: a * b + c rounded once to format fmt (operands of that format)."""
+    return lib().oracle_low_fma(float(a), float(b), float(c), int(fmt))
+
+
+def round_exact(hi: float, lo: float, fmt: int) -> float:
+    """O5: the exact value hi + lo (|lo| <= half an FP64 ulp of hi) rounded
+    once to format fmt, ties to even."""
+    return lib().oracle_round_exact(float(hi), float(lo), int(fmt))
+
+
+def corr_rows(X, C, high: int, fmt: int):
+    """O5 for all pairs: the value a flagged pair takes under fallback
+    precision ``high`` (0 FP64, 1 FP32 on the FP32 inputs, 2 the low format
+    ``fmt`` on the quantised inputs), as an (m, k) float64 array."""
+    X, C = _f32(X), _f32(C)
+    m, d = X.shape
+    k = C.shape[0]
+    out = np.empty((m, k), dtype=np.float64)
+    lib().oracle_corr_rows(_ptr(X), m, d, _ptr(C), k, int(high), int(fmt), _ptr(out))
     return out
 
 

@@ -37,6 +37,18 @@
  *                   in FP32 arithmetic may return (Theorem thm:dist-exp applied
  *                   to the quantised inputs, conversion bound C(x,y) of
  *                   Section 4.3).
+ *   O5  corr     -- the value a flagged pair takes under another fallback
+ *                   precision u (eq:fallback-rule with the uniform precision,
+ *                   eq:fallback-rule-mp with u = FP32; Section 6.1 tests
+ *                   both): the direct formula with every operation rounded
+ *                   once, to nearest even, in the target format (difference,
+ *                   then multiply-add of the square onto the running sum, in
+ *                   coordinate order), on the FP32 inputs (u = FP32) or on
+ *                   the quantised inputs (uniform FP16/BF16/FP32).  Rounding
+ *                   of an exact result is written from the format's
+ *                   definition (spacing of the binade, ties to even); exact
+ *                   results come from exact products and error-free sums in
+ *                   FP64.
  *
  * Build: gcc -O2 -ffp-contract=off -fopenmp -shared -fPIC (no fast-math).
  */
@@ -123,6 +135,85 @@ double oracle_round_low(float xf, int fmt) {
 
 void oracle_quantize(const float *in, int64_t count, int fmt, double *out) {
   for (int64_t i = 0; i < count; ++i) out[i] = oracle_round_low(in[i], fmt);
+}
+
+/* ---------------------------------------------------------------------- */
+/* O5: one correctly rounded operation in FP16 / BF16 / FP32               */
+/* ---------------------------------------------------------------------- */
+
+/* The exact value v = hi + lo (hi = v rounded to FP64, so |lo| is at most
+ * half an FP64 ulp of hi) rounded to the nearest value of format fmt
+ * (0 binary16, 1 bfloat16, 2 binary32), ties to even.  hi alone decides,
+ * except when hi lies exactly halfway between two neighbours of the format:
+ * then v lies on the side of lo (a midpoint has at most t+1 significant bits,
+ * so it is an FP64 number, and an FP64 number other than the midpoint is at
+ * least one FP64 ulp away from it, farther than |lo|). */
+double oracle_round_exact(double hi, double lo, int fmt) {
+  if (fmt < 0 || fmt > 2) return NAN;
+  if (isnan(hi) || isinf(hi)) return hi;
+  if (hi == 0.0) return hi; /* then lo is 0 too */
+  int t = FMT_T[fmt], emin = FMT_EMIN[fmt];
+  double ax = fabs(hi);
+  double al = hi < 0 ? -lo : lo; /* lo along the direction of |hi| */
+  int e;
+  frexp(ax, &e);
+  int expo = e - 1;
+  if (expo < emin) expo = emin;
+  double spacing = ldexp(1.0, expo + 1 - t);
+  double qv = ax / spacing; /* exact: division by a power of two */
+  double fl = floor(qv);
+  double r;
+  if (qv - fl == 0.5 && al != 0.0)
+    r = (al > 0.0 ? fl + 1.0 : fl) * spacing;
+  else
+    r = nearbyint(qv) * spacing;
+  if (r > oracle_fmt_max(fmt)) r = INFINITY;
+  return hi < 0 ? -r : r;
+}
+
+/* a - b and a*b + c for values a, b, c of format fmt, rounded once: a*b is
+ * exact in FP64 (at most 2 x 24 significant bits) and the sum is split into
+ * its FP64 rounding and the exact error (Knuth's two-sum). */
+static double two_sum_round(double x, double y, int fmt) {
+  double s = x + y;
+  double yv = s - x;
+  double err = (x - (s - yv)) + (y - yv);
+  return oracle_round_exact(s, err, fmt);
+}
+double oracle_low_sub(double a, double b, int fmt) { return two_sum_round(a, -b, fmt); }
+double oracle_low_fma(double a, double b, double c, int fmt) {
+  return two_sum_round(a * b, c, fmt);
+}
+
+double oracle_sqdist(const float *x, const float *y, int d);
+
+/* The squared distance a flagged pair takes under fallback precision high
+ * (0: FP64 on the FP32 inputs, O1's sum; 1: FP32 on the FP32 inputs; 2: the
+ * low format fmt itself on the quantised inputs) for the low format fmt
+ * (0 FP16, 1 BF16, 2 FP32). */
+double oracle_corr_dist(const float *x, const float *c, int d, int high, int fmt) {
+  if (high == 0) return oracle_sqdist(x, c, d);
+  int f = (high == 1) ? 2 : fmt;
+  double s = 0.0;
+  for (int l = 0; l < d; ++l) {
+    double xv = (double)x[l], cv = (double)c[l];
+    if (high == 2 && fmt != 2) {
+      xv = oracle_round_low(x[l], fmt);
+      cv = oracle_round_low(c[l], fmt);
+    }
+    double t = oracle_low_sub(xv, cv, f);
+    s = oracle_low_fma(t, t, s, f);
+  }
+  return s;
+}
+
+void oracle_corr_rows(const float *X, int64_t m, int d, const float *C, int k,
+                      int high, int fmt, double *out) {
+#pragma omp parallel for schedule(static)
+  for (int64_t i = 0; i < m; ++i)
+    for (int j = 0; j < k; ++j)
+      out[i * (int64_t)k + j] =
+          oracle_corr_dist(X + i * (int64_t)d, C + (int64_t)j * d, d, high, fmt);
 }
 
 /* ---------------------------------------------------------------------- */

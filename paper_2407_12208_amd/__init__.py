@@ -17,6 +17,7 @@ from dataclasses import dataclass
 __all__ = [
     "KM_LOW_FP16", "KM_LOW_BF16", "KM_LOW_FP32", "KM_EXACT64",
     "KM_ALPHA_PAPER_EQ", "KM_ALPHA_PAPER_ALG", "KM_ALPHA_EXPLICIT", "KM_ALPHA_NONE", "KM_ALPHA_HW",
+    "KM_HIGH_FP64", "KM_HIGH_FP32", "KM_HIGH_LOW",
     "KM_SYNC", "KMeansError", "Precision", "Stats", "Problem", "library_path", "lib",
     "Context", "kmeans_context_create", "kmeans_assign", "kmeans_assign_static", "kmeans_update",
     "kmeans_lloyd", "kmeans_solve_batch", "kmeans_pairwise", "kmeans_quantize",
@@ -27,6 +28,7 @@ __all__ = [
 
 KM_LOW_FP16, KM_LOW_BF16, KM_LOW_FP32, KM_EXACT64 = 0, 1, 2, 3
 KM_ALPHA_PAPER_EQ, KM_ALPHA_PAPER_ALG, KM_ALPHA_EXPLICIT, KM_ALPHA_NONE, KM_ALPHA_HW = 0, 1, 2, 3, 4
+KM_HIGH_FP64, KM_HIGH_FP32, KM_HIGH_LOW = 0, 1, 2
 KM_SYNC = 1
 KM_LABELS_HINT = 2
 KM_OK, KM_PENDING = 0, 1
@@ -56,11 +58,12 @@ class KMeansError(RuntimeError):
 
 class Precision(ct.Structure):
     _fields_ = [("low", ct.c_int32), ("alpha_mode", ct.c_int32),
-                ("rho", ct.c_double), ("alpha", ct.c_double)]
+                ("rho", ct.c_double), ("alpha", ct.c_double),
+                ("high", ct.c_int32), ("reserved", ct.c_int32)]
 
     def __init__(self, low=KM_LOW_FP16, alpha_mode=KM_ALPHA_PAPER_EQ, rho=5.0,
-                 alpha=0.0):
-        super().__init__(int(low), int(alpha_mode), float(rho), float(alpha))
+                 alpha=0.0, high=0):
+        super().__init__(int(low), int(alpha_mode), float(rho), float(alpha), int(high), 0)
 
 
 class Stats(ct.Structure):

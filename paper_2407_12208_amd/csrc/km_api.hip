@@ -73,12 +73,15 @@ km_precision precision_or_default(const km_precision* p) {
   q.alpha_mode = KM_ALPHA_PAPER_EQ;
   q.rho = 5.0;
   q.alpha = 0.0;
+  q.high = KM_HIGH_FP64;
+  q.reserved = 0;
   return q;
 }
 
 int32_t validate_precision(const km_precision& p) {
   if (p.low < KM_LOW_FP16 || p.low > KM_EXACT64) return KM_ERR_ARG;
-  if (p.low == KM_EXACT64) return KM_OK;
+  if (p.high < KM_HIGH_FP64 || p.high > KM_HIGH_LOW) return KM_ERR_ARG;
+  if (p.low == KM_EXACT64) return p.high == KM_HIGH_FP64 ? KM_OK : KM_ERR_ARG;
   if (p.alpha_mode < KM_ALPHA_PAPER_EQ || p.alpha_mode > KM_ALPHA_HW) return KM_ERR_ARG;
   if ((p.alpha_mode == KM_ALPHA_PAPER_EQ || p.alpha_mode == KM_ALPHA_PAPER_ALG ||
        p.alpha_mode == KM_ALPHA_HW) && !(p.rho > 2.0))
@@ -134,6 +137,7 @@ void set_small_sweep(AssignPlan& a, int64_t n, int64_t launch_points) {
 AssignPlan plan_assign(const km_precision& p, int64_t n, int d, int k) {
   AssignPlan a{};
   a.low = p.low;
+  a.high = p.high;
   a.DP = padded_dim(d);
   a.k_pad = (k + 31) & ~31;
   const double alpha = alpha_for(p, d);
@@ -235,6 +239,14 @@ hipError_t run_assign(km_context_impl* ctx, const AssignPlan& shape, int mode,
   return run_assign_dev(ctx, shape, mode, d + op, d + os, (int)probs.size(), pre.back(), st);
 }
 
+// Arithmetic of the direct-formula kernel: FP64 unless every pair of a
+// mixed pass is corrected in another precision.
+static int direct_arith(const AssignPlan& a) {
+  if (a.route != Route::Direct64All || a.high == KM_HIGH_FP64) return 0;
+  if (a.high == KM_HIGH_FP32 || a.low == KM_LOW_FP32) return 1;
+  return a.low == KM_LOW_FP16 ? 2 : 3;
+}
+
 // The assignment launch of problems whose descriptors are already on the
 // device, bracketed by timing events when timing is enabled.
 static hipError_t run_assign_dev(km_context_impl* ctx, const AssignPlan& shape, int mode, const void* dp,
@@ -261,8 +273,8 @@ static hipError_t run_assign_dev(km_context_impl* ctx, const AssignPlan& shape, 
       break;
     case Route::Direct64Exact:
     case Route::Direct64All:
-      e = launch_assign_direct64(shape.route == Route::Direct64Exact, mode, (const AssignProb*)dp,
-                                 (const int32_t*)ds, nprob, total_wg, st);
+      e = launch_assign_direct64(shape.route == Route::Direct64Exact, direct_arith(shape), mode,
+                                 (const AssignProb*)dp, (const int32_t*)ds, nprob, total_wg, st);
       break;
   }
   if (e == hipSuccess && ctx->timing) {
@@ -647,6 +659,7 @@ static hipError_t enqueue_pass(km_context_impl* ctx, const AssignPlan& a, const 
   ap.hint = hint ? labels : nullptr;
   ap.gpw = a.gpw;
   ap.alpha = a.alpha_f;
+  ap.high = a.high;
   const int nwg = mode == 0 ? a.nwg : a.nwg_pair;
   const int32_t apre[2] = {0, nwg};
   const size_t o_ap = pk.add(&ap, sizeof(ap));
@@ -936,7 +949,9 @@ hipError_t enqueue_batch_pass(km_context_impl* ctx, std::vector<BatchState*>& li
     std::vector<int> nw;
     for (size_t j = i; j < list.size(); ++j) {
       const AssignPlan& o = list[j]->plan;
-      if (taken[j] || o.route != sh.route || o.DP != sh.DP || o.low != sh.low || o.xd != sh.xd) continue;
+      if (taken[j] || o.route != sh.route || o.DP != sh.DP || o.low != sh.low || o.xd != sh.xd ||
+          o.high != sh.high)
+        continue;
       // the final pass refines and sums the SSE per workgroup: the problem's
       // own partition, as when it runs alone
       const int gpw = final_pass ? o.gpw_own : o.gpw;
@@ -963,6 +978,7 @@ hipError_t enqueue_batch_pass(km_context_impl* ctx, std::vector<BatchState*>& li
       a.hint = s->it > 0 ? s->prob->labels : nullptr;  // the previous round's labels
       a.gpw = gpw;
       a.alpha = o.alpha_f;
+      a.high = o.high;
       ap.push_back(a);
       nw.push_back(nwg);
     }

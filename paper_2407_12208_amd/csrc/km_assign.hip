@@ -29,6 +29,23 @@ __device__ __noinline__ double sqdist64_call(const float* __restrict__ x, const 
   return sqdist64(x, c, d);
 }
 
+__device__ __noinline__ double corr_dist_call(int high, int fmt, const float* x, const float* c, int d) {
+  return high == kHigh64 ? sqdist64(x, c, d) : corr_dist(high, fmt, x, c, d);
+}
+
+// Correction of a flagged pair in the problem's correction precision: one
+// out-of-line call with the arguments of the plain FP64 one (d and the
+// precision share a register; d < 2^16), so the sweep keeps its registers.
+template <class L>
+__device__ __noinline__ double correct_pair_call(const float* x, const float* c, int d_high) {
+  const int d = d_high & 0xffff, high = d_high >> 16;
+  return high == kHigh64 ? sqdist64(x, c, d) : corr_dist(high, L::kFmt, x, c, d);
+}
+template <class L>
+__device__ inline double correct_pair(const AssignProb& P, const float* x, const float* c, int d) {
+  return correct_pair_call<L>(x, c, d | (P.high << 16));
+}
+
 // Maximum of the 16 accumulator registers (a v_max3 tree).
 __device__ inline float max16(const f32x16& v) {
   const float a = __builtin_fmaxf(__builtin_fmaxf(v[0], v[1]), v[2]);
@@ -317,7 +334,9 @@ k_assign_mfma(const AssignProb* __restrict__ probs, const int32_t* __restrict__ 
         const int j = e & 0xffffff;
         const int cbq = e >> 24;
         const int pl = pw + cbq * 32 + (lane & 31);
-        const double dd = sqdist64(P.X + (p0 + pl) * d, P.C + (int64_t)j * d, d);
+        const double dd = P.high == kHigh64 ? sqdist64(P.X + (p0 + pl) * d, P.C + (int64_t)j * d, d)
+                                            : corr_dist_call(P.high, L::kFmt, P.X + (p0 + pl) * d,
+                                                             P.C + (int64_t)j * d, d);
         const float df = (float)dd;
         ncorr += 1;
 #pragma unroll
@@ -781,7 +800,7 @@ k_assign_pipe(const AssignProb* __restrict__ probs, const int32_t* __restrict__ 
         if ((w + delta) + caj + delta < hx[cb]) bw[cb] = w - 2.0f * delta;
         if constexpr (kPreCorrect) {
           if ((w - delta) + caj - delta >= hx[cb] && (lane >> 5) == ((h >> 2) & 1)) {
-            const float df = (float)sqdist64_call(P.X + (p0 + pl) * d, P.C + (int64_t)h * d, d);
+            const float df = (float)correct_pair<L>(P, P.X + (p0 + pl) * d, P.C + (int64_t)h * d, d);
             ncorr += 1;
             cd[cb] = df;
             cj[cb] = h;
@@ -799,7 +818,7 @@ k_assign_pipe(const AssignProb* __restrict__ probs, const int32_t* __restrict__ 
         const int j = e & 0xffffff;
         const int cbq = e >> 24;
         const int pl = pw + cbq * 32 + (lane & 31);
-        const double dd = sqdist64_call(P.X + (p0 + pl) * d, P.C + (int64_t)j * d, d);
+        const double dd = correct_pair<L>(P, P.X + (p0 + pl) * d, P.C + (int64_t)j * d, d);
         const float df = (float)dd;
         ncorr += 1;
 #pragma unroll
@@ -947,7 +966,7 @@ k_assign_pipe(const AssignProb* __restrict__ probs, const int32_t* __restrict__ 
               s_q[qn * NT + tid] = j | (cb << 24);
               qn += 1;
             } else {  // queue full (dense flags): correct this pair now
-              const float df = (float)sqdist64_call(P.X + (p0 + pl) * d, P.C + (int64_t)j * d, d);
+              const float df = (float)correct_pair<L>(P, P.X + (p0 + pl) * d, P.C + (int64_t)j * d, d);
               ncorr += 1;
               if (df < cd[cb] || (df == cd[cb] && j < cj[cb])) {
                 cd[cb] = df;
@@ -1391,16 +1410,20 @@ k_assign_small(const AssignProb* __restrict__ probs, const int32_t* __restrict__
             // four coordinates per LDS access; both rows are zero past d,
             // and a zero term leaves the FP64 sum unchanged
             double sq = 0.0;
+            if (P.high == kHigh64) {
 #pragma unroll
-            for (int l0 = 0; l0 < XD; l0 += 4) {
-              if (l0 >= d) break;
-              const f32x4 a4 = *reinterpret_cast<const f32x4*>(xr + l0);
-              const f32x4 c4 = *reinterpret_cast<const f32x4*>(cr + l0);
+              for (int l0 = 0; l0 < XD; l0 += 4) {
+                if (l0 >= d) break;
+                const f32x4 a4 = *reinterpret_cast<const f32x4*>(xr + l0);
+                const f32x4 c4 = *reinterpret_cast<const f32x4*>(cr + l0);
 #pragma unroll
-              for (int e = 0; e < 4; ++e) {
-                const double t = (double)a4[e] - (double)c4[e];
-                sq = __builtin_fma(t, t, sq);
+                for (int e = 0; e < 4; ++e) {
+                  const double t = (double)a4[e] - (double)c4[e];
+                  sq = __builtin_fma(t, t, sq);
+                }
               }
+            } else {
+              sq = corr_dist(P.high, L::kFmt, xr, cr, d);
             }
             // smallest value, then lowest index: FP32 bits of a
             // non-negative value order like the value
@@ -1475,14 +1498,58 @@ k_assign_small(const AssignProb* __restrict__ probs, const int32_t* __restrict__
 }
 
 // ---------------------------------------------------------------------------
-// Every pair by the FP64 direct formula.  64 points x 64 centres per step,
-// 256 threads each owning a 4 x 4 block of pairs; FP32 tiles in LDS.
+// Every pair by the direct formula.  64 points x 64 centres per step, 256
+// threads each owning a 4 x 4 block of pairs; FP32 tiles in LDS.
 // CMP64: compare the FP64 values (plain FP64 kernel); otherwise compare the
 // values rounded to FP32 (mixed path with every pair corrected).
+// AR: arithmetic of the formula -- 0 FP64; 1 FP32; 2 binary16 and 3 bfloat16
+// on the rounded inputs (every operation rounded once, coordinates in
+// order), for the other correction precisions when every pair is flagged.
 // ---------------------------------------------------------------------------
-template <bool CMP64, int MODE>
+template <int AR>
+struct DirectArith;
+template <>
+struct DirectArith<0> {
+  using T = double;
+  __device__ static inline T in(float v) { return (double)v; }
+  __device__ static inline T step(T x, T c, T s) {
+    const double e = x - c;
+    return __builtin_fma(e, e, s);
+  }
+};
+template <>
+struct DirectArith<1> {
+  using T = float;
+  __device__ static inline T in(float v) { return v; }
+  __device__ static inline T step(T x, T c, T s) {
+    const float e = x - c;
+    return __builtin_fmaf(e, e, s);
+  }
+};
+template <>
+struct DirectArith<2> {
+  using T = _Float16;
+  __device__ static inline T in(float v) { return (_Float16)v; }
+  __device__ static inline T step(T x, T c, T s) {
+    const _Float16 e = x - c;
+    return __builtin_fmaf16(e, e, s);
+  }
+};
+template <>
+struct DirectArith<3> {
+  using T = float;  // bfloat16 values held in FP32
+  __device__ static inline T in(float v) { return (float)(__bf16)v; }
+  __device__ static inline T step(T x, T c, T s) {
+    const float e = bf16_sub(x, c);
+    return bf16_fma(e, e, s);
+  }
+};
+
+template <bool CMP64, int MODE, int AR>
 __global__ void __launch_bounds__(256)
 k_assign_direct64(const AssignProb* __restrict__ probs, const int32_t* __restrict__ wg_start, int nprob) {
+  using A = DirectArith<AR>;
+  using T = typename A::T;
   constexpr int TP = 64, TC = 64, DC = 32;  // points, centres, coordinates per chunk
   __shared__ float sxs[TP][DC + 1];
   __shared__ float scs[TC][DC + 1];
@@ -1509,11 +1576,11 @@ k_assign_direct64(const AssignProb* __restrict__ probs, const int32_t* __restric
     bidx[a] = -1;
   }
   for (int c0 = 0; c0 < k; c0 += TC) {
-    double acc[4][4];
+    T acc[4][4];
 #pragma unroll
     for (int a = 0; a < 4; ++a)
 #pragma unroll
-      for (int b = 0; b < 4; ++b) acc[a][b] = 0.0;
+      for (int b = 0; b < 4; ++b) acc[a][b] = (T)0.0f;
     for (int l0 = 0; l0 < d; l0 += DC) {
       __syncthreads();
       for (int e = tid; e < TP * DC; e += 256) {
@@ -1523,28 +1590,29 @@ k_assign_direct64(const AssignProb* __restrict__ probs, const int32_t* __restric
           v = as_global(P.X)[(p0 + p) * d + l0 + l];
           if (c0 == 0) {
             if (!__builtin_isfinite(v)) bad |= kStatusNonFinite;
+            if (AR == 2 && __builtin_fabsf(v) >= LowF16::kOverflow) bad |= kStatusRange;
           }
         }
         sxs[p][l] = v;
         float w = 0.f;
-        if (c0 + p < k && l0 + l < d) w = as_global(P.C)[(int64_t)(c0 + p) * d + l0 + l];
+        if (c0 + p < k && l0 + l < d) {
+          w = as_global(P.C)[(int64_t)(c0 + p) * d + l0 + l];
+          if (AR == 2 && __builtin_fabsf(w) >= LowF16::kOverflow) bad |= kStatusRange;
+        }
         scs[p][l] = w;
       }
       __syncthreads();
       const int lmax = (d - l0) < DC ? (d - l0) : DC;
       for (int l = 0; l < lmax; ++l) {
-        double xv[4], cv[4];
+        T xv[4], cv[4];
 #pragma unroll
-        for (int a = 0; a < 4; ++a) xv[a] = (double)sxs[pg * 4 + a][l];
+        for (int a = 0; a < 4; ++a) xv[a] = A::in(sxs[pg * 4 + a][l]);
 #pragma unroll
-        for (int b = 0; b < 4; ++b) cv[b] = (double)scs[cg * 4 + b][l];
+        for (int b = 0; b < 4; ++b) cv[b] = A::in(scs[cg * 4 + b][l]);
 #pragma unroll
         for (int a = 0; a < 4; ++a)
 #pragma unroll
-          for (int b = 0; b < 4; ++b) {
-            const double e = xv[a] - cv[b];
-            acc[a][b] = __builtin_fma(e, e, acc[a][b]);
-          }
+          for (int b = 0; b < 4; ++b) acc[a][b] = A::step(xv[a], cv[b], acc[a][b]);
       }
     }
 #pragma unroll
@@ -1555,7 +1623,7 @@ k_assign_direct64(const AssignProb* __restrict__ probs, const int32_t* __restric
         const int p = pg * 4 + a;
         if (j < k && p < nvalid) {
           if constexpr (MODE == 0) {
-            const double v = CMP64 ? acc[a][b] : (double)(float)acc[a][b];
+            const double v = CMP64 ? (double)acc[a][b] : (double)(float)acc[a][b];
             if (v < best[a]) {  // centres visited in increasing order
               best[a] = v;
               bidx[a] = j;
@@ -1759,14 +1827,28 @@ hipError_t launch_assign_small(int low, int xd, bool fallback, const AssignProb*
   return hipErrorInvalidValue;
 }
 
-hipError_t launch_assign_direct64(bool cmp64, int mode, const AssignProb* dprobs, const int32_t* dstart,
-                                  int nprob, int nwg, hipStream_t st) {
-  if (mode == 0) {
-    if (cmp64) hipLaunchKernelGGL((k_assign_direct64<true, 0>), dim3(nwg), dim3(256), 0, st, dprobs, dstart, nprob);
-    else hipLaunchKernelGGL((k_assign_direct64<false, 0>), dim3(nwg), dim3(256), 0, st, dprobs, dstart, nprob);
-  } else {
-    hipLaunchKernelGGL((k_assign_direct64<true, 1>), dim3(nwg), dim3(256), 0, st, dprobs, dstart, nprob);
+hipError_t launch_assign_direct64(bool cmp64, int arith, int mode, const AssignProb* dprobs,
+                                  const int32_t* dstart, int nprob, int nwg, hipStream_t st) {
+#define KM_DIRECT(C, M, AR) \
+  hipLaunchKernelGGL((k_assign_direct64<C, M, AR>), dim3(nwg), dim3(256), 0, st, dprobs, dstart, nprob)
+  if (cmp64) {
+    if (arith != 0) return hipErrorInvalidValue;
+    if (mode == 0) KM_DIRECT(true, 0, 0);
+    else KM_DIRECT(true, 1, 0);
+    return hipGetLastError();
   }
+  switch (arith * 2 + (mode != 0)) {
+    case 0: KM_DIRECT(false, 0, 0); break;
+    case 1: KM_DIRECT(true, 1, 0); break;  // materialised values are the same
+    case 2: KM_DIRECT(false, 0, 1); break;
+    case 3: KM_DIRECT(true, 1, 1); break;
+    case 4: KM_DIRECT(false, 0, 2); break;
+    case 5: KM_DIRECT(true, 1, 2); break;
+    case 6: KM_DIRECT(false, 0, 3); break;
+    case 7: KM_DIRECT(true, 1, 3); break;
+    default: return hipErrorInvalidValue;
+  }
+#undef KM_DIRECT
   return hipGetLastError();
 }
 

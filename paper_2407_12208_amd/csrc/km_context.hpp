@@ -119,6 +119,7 @@ enum class Route { Mfma, MfmaNoFallback, Direct64Exact, Direct64All };
 struct AssignPlan {
   Route route;
   int low;
+  int high;         // correction precision (KM_HIGH_*)
   int DP;
   int k_pad;
   int xd;           // > 0: the small-problem kernel with this row capacity

@@ -44,6 +44,7 @@ __device__ __forceinline__ KM_GLOBAL T* as_global(T* p) {
 //   D: column (l % 32), rows 8*(r/4) + 4*(l/32) + (r%4) for r = 0..15
 // ---------------------------------------------------------------------------
 struct LowF16 {
+  static constexpr int kFmt = 0;
   using S = _Float16;
   using frag = f16x8;
   static constexpr int KS = 16, KV = 8;
@@ -59,6 +60,7 @@ struct LowF16 {
 };
 
 struct LowBF16 {
+  static constexpr int kFmt = 1;
   using S = __bf16;
   using frag = bf16x8;
   static constexpr int KS = 16, KV = 8;
@@ -73,6 +75,7 @@ struct LowBF16 {
 };
 
 struct LowF32 {
+  static constexpr int kFmt = 2;
   using S = float;
   using frag = float;
   static constexpr int KS = 2, KV = 1;
@@ -126,6 +129,103 @@ __device__ inline double sqdist64(const float* __restrict__ xp,
 // Out-of-line copy for rare paths (keeps the hot loops compact).
 __device__ __noinline__ double sqdist64_call(const float* __restrict__ x,
                                             const float* __restrict__ c, int d);
+
+// ---------------------------------------------------------------------------
+// Other correction precisions of a flagged pair (the fallback rules
+// eq:fallback-rule and eq:fallback-rule-mp with another precision u):
+//   kHigh64  -- the FP64 direct formula on the FP32 inputs (default);
+//   kHigh32  -- the FP32 direct formula on the FP32 inputs;
+//   kHighLow -- the direct formula in the low format itself, on the
+//               quantised inputs x~, c~ (the uniform rule eq:fallback-rule).
+// Every operation is one correctly rounded operation of the format
+// (round to nearest even): differences, then a fused multiply-add per
+// coordinate in index order.
+// ---------------------------------------------------------------------------
+constexpr int kHigh64 = 0, kHigh32 = 1, kHighLow = 2;
+
+// FP32 direct formula, coordinates in index order.
+__device__ inline float sqdist32(const float* x, const float* c, int d) {
+  float s = 0.0f;
+  for (int l = 0; l < d; ++l) {
+    const float t = x[l] - c[l];
+    s = __builtin_fmaf(t, t, s);
+  }
+  return s;
+}
+
+// binary16 direct formula on x~ = RNE16(x), c~ = RNE16(c): the hardware's
+// half-precision subtraction and fused multiply-add round once each.
+__device__ inline float sqdist16(const float* x, const float* c, int d) {
+  _Float16 s = (_Float16)0.0f;
+  for (int l = 0; l < d; ++l) {
+    const _Float16 t = (_Float16)x[l] - (_Float16)c[l];
+    s = __builtin_fmaf16(t, t, s);
+  }
+  return (float)s;
+}
+
+// One rounding of the exact value hi + lo to bfloat16 (returned as FP32),
+// where hi = RN64(hi + lo).  hi is first rounded to FP32; that can land on a
+// bfloat16 midpoint that the exact value does not lie on, and only then does
+// the remainder (hi - f) + lo decide the direction.
+__device__ inline float bf16_round(double hi, double lo) {
+  const float f = (float)hi;
+  uint32_t b = __float_as_uint(f);
+  if ((b & 0xffffu) == 0x8000u && (b & 0x7f800000u) != 0x7f800000u) {
+    const double rem = (hi - (double)f) + lo;  // hi - f is exact
+    if (rem != 0.0) {
+      const bool up = (rem > 0.0) == (f > 0.0);  // away from zero
+      return __uint_as_float(up ? (b + 0x8000u) : (b & 0xffff0000u));
+    }
+  }
+  if ((b & 0x7f800000u) == 0x7f800000u) return f;  // inf (no NaN arises here)
+  b += 0x7fffu + ((b >> 16) & 1u);
+  return __uint_as_float(b & 0xffff0000u);
+}
+
+// bfloat16 a - b and a * b + c for bfloat16 operands held in FP32: the exact
+// result as an unevaluated FP64 sum (two-sum; a * b is exact in FP64), one
+// rounding.
+__device__ inline float bf16_sub(float a, float b) {
+  const double x = (double)a, y = -(double)b;
+  const double s = x + y;
+  const double yv = s - x;
+  const double e = (x - (s - yv)) + (y - yv);
+  return bf16_round(s, e);
+}
+__device__ inline float bf16_fma(float a, float b, float c) {
+  const double x = (double)a * (double)b, y = (double)c;
+  const double s = x + y;
+  const double yv = s - x;
+  const double e = (x - (s - yv)) + (y - yv);
+  return bf16_round(s, e);
+}
+
+// bfloat16 direct formula on x~ = RNE_bf16(x), c~ = RNE_bf16(c).
+__device__ inline float sqdistbf16(const float* x, const float* c, int d) {
+  float s = 0.0f;
+  for (int l = 0; l < d; ++l) {
+    const float t = bf16_sub((float)(__bf16)x[l], (float)(__bf16)c[l]);
+    s = bf16_fma(t, t, s);
+  }
+  return s;
+}
+
+// Corrected squared distance in the requested precision (fmt: 0 FP16,
+// 1 BF16, 2 FP32 low format).  The FP32 and low-format values are exact in
+// FP64.
+__device__ inline double corr_dist(int high, int fmt, const float* x, const float* c, int d) {
+  if (high == kHigh32 || (high == kHighLow && fmt == 2)) return (double)sqdist32(x, c, d);
+  if (high == kHighLow) return (double)(fmt == 0 ? sqdist16(x, c, d) : sqdistbf16(x, c, d));
+  double s = 0.0;
+  for (int l = 0; l < d; ++l) {
+    const double e = (double)x[l] - (double)c[l];
+    s = __builtin_fma(e, e, s);
+  }
+  return s;
+}
+// Out-of-line, for x and c in global memory (FP64 through sqdist64).
+__device__ __noinline__ double corr_dist_call(int high, int fmt, const float* x, const float* c, int d);
 
 // Wavefront sum of a double in a fixed butterfly order (deterministic).
 __device__ inline double wave_sum(double v) {

@@ -87,6 +87,7 @@ struct AssignProb {
   const int32_t* hint;  // nullable: an earlier assignment (seeds the search)
   int gpw;              // small-problem kernel: 32-point groups per wave
   float alpha;          // small-problem kernel: alpha (FP32), for its own centre constants
+  int high;             // correction precision of flagged pairs (kHigh64 / kHigh32 / kHighLow)
 };
 
 struct ReduceProb {
@@ -135,8 +136,9 @@ hipError_t launch_assign_mfma(int low, int DP, int mode, bool fallback, const As
                               const int32_t* dstart, int nprob, int nwg, hipStream_t st);
 hipError_t launch_assign_small(int low, int xd, bool fallback, const AssignProb* dprobs, const int32_t* dstart,
                                int nprob, int nwg, hipStream_t st);
-hipError_t launch_assign_direct64(bool cmp64, int mode, const AssignProb* dprobs, const int32_t* dstart,
-                                  int nprob, int nwg, hipStream_t st);
+// arith: 0 FP64, 1 FP32, 2 binary16, 3 bfloat16 (direct formula arithmetic)
+hipError_t launch_assign_direct64(bool cmp64, int arith, int mode, const AssignProb* dprobs,
+                                  const int32_t* dstart, int nprob, int nwg, hipStream_t st);
 hipError_t launch_reduce_parts(const ReduceProb* dprobs, int nprob, hipStream_t st);
 hipError_t launch_gather_results(const KResult* const* dsrc, int count, KResult* ddst, hipStream_t st);
 hipError_t launch_zero_words(void* p, size_t bytes, hipStream_t st);  // bytes rounded up to 4

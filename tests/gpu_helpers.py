@@ -170,3 +170,72 @@ def check_assignment_scan(scan, t, labels, mindist, sse, n_corrected, *, bound="
         assert c[0] <= n_corrected <= c[0] + c[1], \
             "corrected %d not in [%d, %d]" % (n_corrected, c[0], c[0] + c[1])
     return rep
+
+
+def corr_intervals(X, C, fmt, alpha, high):
+    """Per pair, the interval the value a GPU pass compares may take under
+    correction precision ``high`` (0 FP64, 1 FP32, 2 the low format): a
+    surely corrected pair takes exactly O5's value (FP64 rounded once to
+    FP32; FP32 and low-format values are FP32 numbers), a surely kept pair
+    lies within O4's bound A of the quantised distance q (FP16/BF16) or
+    within A + 2 u_32 dist of dist (FP32 inputs), an ambiguous pair may take
+    either.  Returns (lo, hi, cls, h32, dist)."""
+    X = np.ascontiguousarray(X, dtype=np.float32)
+    C = np.ascontiguousarray(C, dtype=np.float32)
+    h32 = oracle.corr_rows(X, C, high, fmt).astype(np.float32).astype(np.float64)
+    if fmt in (0, 1):
+        r = oracle.mp_rows(X, C, fmt, alpha)
+        dist, cls = r["dist"], r["cls"]
+        klo = r["q"] - r["A"] * (1 + 1e-9) - 1e-30
+        khi = r["q"] + r["A"] * (1 + 1e-9) + 1e-30
+    else:
+        dist = oracle.dist_rows(X, C)
+        u32 = oracle.unit_roundoff(2)
+        xn = (X.astype(np.float64) ** 2).sum(1)[:, None]
+        cn = (C.astype(np.float64) ** 2).sum(1)[None, :]
+        P = np.abs(X.astype(np.float64)) @ np.abs(C.astype(np.float64)).T
+        A = oracle.gamma(X.shape[1] + 4, 2 * u32) * (xn + cn + 2 * P)
+        Bk = A + 2 * u32 * dist
+        klo, khi = dist - Bk, dist + Bk
+        margin = dist - alpha * (xn + cn)
+        band = (1 + alpha) * A + 2 * u32 * dist
+        cls = np.where(margin < -band, -1, np.where(margin > band, 1, 0)).astype(np.int8)
+    klo = np.maximum(klo, 0.0)  # kept values are clamped at zero
+    lo = np.where(cls == -1, h32, np.where(cls == 1, klo, np.minimum(h32, klo)))
+    hi = np.where(cls == -1, h32, np.where(cls == 1, khi, np.maximum(h32, khi)))
+    return lo, hi, cls, h32, dist
+
+
+def check_assignment_high(X, C, fmt, alpha, high, labels, mindist, n_corrected, min_coverage=0.0):
+    """Labels of a pass with correction precision ``high``: the returned label
+    can be a minimiser of the compared values (its interval starts at or
+    below the smallest interval end of the row), equals the only such centre
+    where there is one, and is the lowest index when every candidate is a
+    corrected pair of the same value.  mindist is the FP64 refinement of the
+    returned label; the corrected-pair count lies between the surely
+    corrected and the surely corrected plus ambiguous pairs."""
+    lo, hi, cls, h32, dist = corr_intervals(X, C, fmt, alpha, high)
+    lab = np.asarray(labels).astype(np.int64)
+    m = lo.shape[0]
+    ii = np.arange(m)
+    H = hi.min(axis=1)
+    cand = lo <= H[:, None]
+    assert np.all(cand[ii, lab]), "label not a possible minimiser at rows %s" % (
+        np.nonzero(~cand[ii, lab])[0][:5])
+    ncand = cand.sum(axis=1)
+    single = ncand == 1
+    first = np.argmax(cand, axis=1)
+    assert np.all(lab[single] == first[single])
+    pts = np.all(~cand | ((cls == -1) & (h32 == H[:, None])), axis=1) & ~single
+    assert np.all(lab[pts] == first[pts]), "tie of corrected values not resolved to the lowest index"
+    coverage = float(single.mean())
+    assert coverage >= min_coverage, "gate coverage %.4f < %.4f" % (coverage, min_coverage)
+    if mindist is not None:
+        md = np.asarray(mindist).astype(np.float64)
+        d_lab = dist[ii, lab]
+        assert np.all(np.abs(md - d_lab) <= DIST_RTOL * d_lab + 1e-30), "mindist is not the FP64 value"
+    n_sure, n_amb = int((cls == -1).sum()), int((cls == 0).sum())
+    if n_corrected is not None:
+        assert n_sure <= n_corrected <= n_sure + n_amb, \
+            "corrected %d not in [%d, %d]" % (n_corrected, n_sure, n_sure + n_amb)
+    return dict(coverage=coverage, ties=int(pts.sum()), n_sure=n_sure, n_amb=n_amb)
