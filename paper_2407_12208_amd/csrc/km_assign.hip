@@ -1498,8 +1498,7 @@ k_assign_small(const AssignProb* __restrict__ probs, const int32_t* __restrict__
 }
 
 // ---------------------------------------------------------------------------
-// Every pair by the direct formula.  64 points x 64 centres per step, 256
-// threads each owning a 4 x 4 block of pairs; FP32 tiles in LDS.
+// Every pair by the direct formula (tiles described below).
 // CMP64: compare the FP64 values (plain FP64 kernel); otherwise compare the
 // values rounded to FP32 (mixed path with every pair corrected).
 // AR: arithmetic of the formula -- 0 FP64; 1 FP32; 2 binary16 and 3 bfloat16
@@ -1512,47 +1511,50 @@ template <>
 struct DirectArith<0> {
   using T = double;
   __device__ static inline T in(float v) { return (double)v; }
-  __device__ static inline T step(T x, T c, T s) {
-    const double e = x - c;
-    return __builtin_fma(e, e, s);
-  }
+  __device__ static inline T step(T x, T c, T s) { return acc(diff(x, c), s); }
+  __device__ static inline T diff(T x, T c) { return x - c; }
+  __device__ static inline T acc(T e, T s) { return __builtin_fma(e, e, s); }
 };
 template <>
 struct DirectArith<1> {
   using T = float;
   __device__ static inline T in(float v) { return v; }
-  __device__ static inline T step(T x, T c, T s) {
-    const float e = x - c;
-    return __builtin_fmaf(e, e, s);
-  }
+  __device__ static inline T step(T x, T c, T s) { return acc(diff(x, c), s); }
+  __device__ static inline T diff(T x, T c) { return x - c; }
+  __device__ static inline T acc(T e, T s) { return __builtin_fmaf(e, e, s); }
 };
 template <>
 struct DirectArith<2> {
   using T = _Float16;
   __device__ static inline T in(float v) { return (_Float16)v; }
-  __device__ static inline T step(T x, T c, T s) {
-    const _Float16 e = x - c;
-    return __builtin_fmaf16(e, e, s);
-  }
+  __device__ static inline T step(T x, T c, T s) { return acc(diff(x, c), s); }
+  __device__ static inline T diff(T x, T c) { return x - c; }
+  __device__ static inline T acc(T e, T s) { return __builtin_fmaf16(e, e, s); }
 };
 template <>
 struct DirectArith<3> {
   using T = float;  // bfloat16 values held in FP32
   __device__ static inline T in(float v) { return (float)(__bf16)v; }
-  __device__ static inline T step(T x, T c, T s) {
-    const float e = bf16_sub(x, c);
-    return bf16_fma(e, e, s);
-  }
+  __device__ static inline T step(T x, T c, T s) { return acc(diff(x, c), s); }
+  __device__ static inline T diff(T x, T c) { return bf16_sub(x, c); }
+  __device__ static inline T acc(T e, T s) { return bf16_fma(e, e, s); }
 };
 
+// 128 points x 128 centres per step; thread (pg, cg) owns points pg*8.. and
+// centres cg*8.. (8 x 8 pairs in registers).  Coordinate chunks of 16 are
+// staged in LDS already converted to the arithmetic type, coordinate-major,
+// so each thread reads its 8 points and 8 centres of a coordinate with wide
+// loads; per coordinate a thread issues 64 subtractions and 64 FMAs.  The
+// sum of a pair runs over the coordinates in index order.
 template <bool CMP64, int MODE, int AR>
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(256, 2)  // two workgroups per CU: <= 256 VGPRs
 k_assign_direct64(const AssignProb* __restrict__ probs, const int32_t* __restrict__ wg_start, int nprob) {
   using A = DirectArith<AR>;
   using T = typename A::T;
-  constexpr int TP = 64, TC = 64, DC = 32;  // points, centres, coordinates per chunk
-  __shared__ float sxs[TP][DC + 1];
-  __shared__ float scs[TC][DC + 1];
+  constexpr int TP = kDirectPointsPerWg, TC = 128, DC = 16, RB = 8;
+  static_assert(TP == 128, "tile");
+  __shared__ __attribute__((aligned(16))) T sx[DC][TP];
+  __shared__ __attribute__((aligned(16))) T sc[DC][TC];
   __shared__ double s_best[16][TP];
   __shared__ int s_bidx[16][TP];
   __shared__ double s_sse[4];
@@ -1565,68 +1567,117 @@ k_assign_direct64(const AssignProb* __restrict__ probs, const int32_t* __restric
   const int64_t p0 = (int64_t)tile * TP;
   const int d = P.d, k = P.k;
   const int nvalid = (int)((P.n - p0) < TP ? (P.n - p0) : TP);
-  const int pg = tid & 15, cg = tid >> 4;  // points pg*4.., centres cg*4..
+  const int pg = tid & 15, cg = tid >> 4;  // points pg*8.., centres cg*8..
+  const bool vec = (d & 3) == 0 && ((((uintptr_t)P.X) | ((uintptr_t)P.C)) & 15) == 0;
 
   int bad = 0;
-  double best[4];
-  int bidx[4];
+  // each thread's best centre per point so far lives in its own LDS slots
+  // (registers go to the 8 x 8 sums)
 #pragma unroll
-  for (int a = 0; a < 4; ++a) {
-    best[a] = __builtin_inf();
-    bidx[a] = -1;
+  for (int a = 0; a < RB; ++a) {
+    s_best[cg][pg * RB + a] = __builtin_inf();
+    s_bidx[cg][pg * RB + a] = -1;
   }
-  for (int c0 = 0; c0 < k; c0 += TC) {
-    T acc[4][4];
+  // The next chunk's coordinates are loaded into registers while the
+  // current chunk is computed: loads of chunk (c0, l0) are issued one chunk
+  // ahead and written to LDS (converted) between two barriers.
+  constexpr int NS = TP * DC / 256;  // elements per thread and chunk (8)
+  static_assert(NS == 8, "two quads per thread");
+  float xr[NS], cr[NS];  // vector path: quads r = 0, 1 in elements 4r..4r+3
+  auto fetch = [&](int c0f, int l0f) __attribute__((always_inline)) {
+    if (vec) {
 #pragma unroll
-    for (int a = 0; a < 4; ++a)
+      for (int r = 0; r < 2; ++r) {
+        const int e = tid + 256 * r, p = e >> 2, q = e & 3;
+        f32x4 a = f32x4{0.f, 0.f, 0.f, 0.f}, b = f32x4{0.f, 0.f, 0.f, 0.f};
+        if (p < nvalid && l0f + 4 * q < d)
+          a = *reinterpret_cast<const KM_GLOBAL f32x4*>(as_global(P.X) + (p0 + p) * d + l0f + 4 * q);
+        if (c0f + p < k && l0f + 4 * q < d)
+          b = *reinterpret_cast<const KM_GLOBAL f32x4*>(as_global(P.C) + (int64_t)(c0f + p) * d + l0f + 4 * q);
 #pragma unroll
-      for (int b = 0; b < 4; ++b) acc[a][b] = (T)0.0f;
-    for (int l0 = 0; l0 < d; l0 += DC) {
-      __syncthreads();
-      for (int e = tid; e < TP * DC; e += 256) {
-        const int p = e / DC, l = e % DC;
-        float v = 0.f;
-        if (p < nvalid && l0 + l < d) {
-          v = as_global(P.X)[(p0 + p) * d + l0 + l];
-          if (c0 == 0) {
-            if (!__builtin_isfinite(v)) bad |= kStatusNonFinite;
-            if (AR == 2 && __builtin_fabsf(v) >= LowF16::kOverflow) bad |= kStatusRange;
-          }
+        for (int i = 0; i < 4; ++i) {
+          xr[4 * r + i] = a[i];
+          cr[4 * r + i] = b[i];
         }
-        sxs[p][l] = v;
-        float w = 0.f;
-        if (c0 + p < k && l0 + l < d) {
-          w = as_global(P.C)[(int64_t)(c0 + p) * d + l0 + l];
-          if (AR == 2 && __builtin_fabsf(w) >= LowF16::kOverflow) bad |= kStatusRange;
-        }
-        scs[p][l] = w;
       }
+    } else {
+#pragma unroll
+      for (int r = 0; r < NS; ++r) {
+        const int e = tid + 256 * r, p = e / DC, l = e - p * DC;
+        xr[r] = (p < nvalid && l0f + l < d) ? as_global(P.X)[(p0 + p) * d + l0f + l] : 0.f;
+        cr[r] = (c0f + p < k && l0f + l < d) ? as_global(P.C)[(int64_t)(c0f + p) * d + l0f + l] : 0.f;
+      }
+    }
+  };
+  auto stage = [&](bool first_tile) __attribute__((always_inline)) {
+#pragma unroll
+    for (int r = 0; r < NS; ++r) {
+      const float v = xr[r], w = cr[r];
+      if (first_tile && !__builtin_isfinite(v)) bad |= kStatusNonFinite;
+      if (AR == 2 && (__builtin_fabsf(v) >= LowF16::kOverflow || __builtin_fabsf(w) >= LowF16::kOverflow))
+        bad |= kStatusRange;
+      int p, l;
+      if (vec) {
+        const int e = tid + 256 * (r >> 2);
+        p = e >> 2;
+        l = 4 * (e & 3) + (r & 3);
+      } else {
+        const int e = tid + 256 * r;
+        p = e / DC;
+        l = e - p * DC;
+      }
+      sx[l][p] = A::in(v);
+      sc[l][p] = A::in(w);
+    }
+  };
+  fetch(0, 0);
+  for (int c0 = 0; c0 < k; c0 += TC) {
+    T acc[RB][RB];
+#pragma unroll
+    for (int a = 0; a < RB; ++a)
+#pragma unroll
+      for (int b = 0; b < RB; ++b) acc[a][b] = (T)0.0f;
+    for (int l0 = 0; l0 < d; l0 += DC) {
+      // zero past the ends: a zero difference leaves a sum unchanged
       __syncthreads();
+      stage(c0 == 0);
+      __syncthreads();
+      {
+        const bool more = l0 + DC < d;
+        const int c0n = more ? c0 : c0 + TC, l0n = more ? l0 + DC : 0;
+        if (c0n < k) fetch(c0n, l0n);
+      }
       const int lmax = (d - l0) < DC ? (d - l0) : DC;
       for (int l = 0; l < lmax; ++l) {
-        T xv[4], cv[4];
+        T xv[RB], cv[RB];
 #pragma unroll
-        for (int a = 0; a < 4; ++a) xv[a] = A::in(sxs[pg * 4 + a][l]);
+        for (int a = 0; a < RB; ++a) xv[a] = sx[l][pg * RB + a];
 #pragma unroll
-        for (int b = 0; b < 4; ++b) cv[b] = A::in(scs[cg * 4 + b][l]);
+        for (int b = 0; b < RB; ++b) cv[b] = sc[l][cg * RB + b];
+        // eight independent differences, then their eight multiply-adds
+        // (no subtraction feeds the instruction right after it)
 #pragma unroll
-        for (int a = 0; a < 4; ++a)
+        for (int a = 0; a < RB; ++a) {
+          T e[RB];
 #pragma unroll
-          for (int b = 0; b < 4; ++b) acc[a][b] = A::step(xv[a], cv[b], acc[a][b]);
+          for (int b = 0; b < RB; ++b) e[b] = A::diff(xv[a], cv[b]);
+#pragma unroll
+          for (int b = 0; b < RB; ++b) acc[a][b] = A::acc(e[b], acc[a][b]);
+        }
       }
     }
 #pragma unroll
-    for (int a = 0; a < 4; ++a)
+    for (int a = 0; a < RB; ++a)
 #pragma unroll
-      for (int b = 0; b < 4; ++b) {
-        const int j = c0 + cg * 4 + b;
-        const int p = pg * 4 + a;
+      for (int b = 0; b < RB; ++b) {
+        const int j = c0 + cg * RB + b;
+        const int p = pg * RB + a;
         if (j < k && p < nvalid) {
           if constexpr (MODE == 0) {
             const double v = CMP64 ? (double)acc[a][b] : (double)(float)acc[a][b];
-            if (v < best[a]) {  // centres visited in increasing order
-              best[a] = v;
-              bidx[a] = j;
+            if (v < s_best[cg][p]) {  // centres visited in increasing order
+              s_best[cg][p] = v;
+              s_bidx[cg][p] = j;
             }
           } else {
             const int64_t o = (p0 + p) * (int64_t)k + j;
@@ -1640,11 +1691,6 @@ k_assign_direct64(const AssignProb* __restrict__ probs, const int32_t* __restric
   double sse = 0.0;
   unsigned long long nc = 0;
   if constexpr (MODE == 0) {
-#pragma unroll
-    for (int a = 0; a < 4; ++a) {
-      s_best[cg][pg * 4 + a] = best[a];
-      s_bidx[cg][pg * 4 + a] = bidx[a];
-    }
     __syncthreads();
     if (tid < TP && tid < nvalid) {
       double bv = __builtin_inf();

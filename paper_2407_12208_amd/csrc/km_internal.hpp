@@ -36,7 +36,7 @@ constexpr int kPipeThreads = 64 * kPipeWaves;
 constexpr int pipe_points_per_wg(int low, int DP) { return kPipeWaves * 32 * mfma_nb(low, DP); }
 // points per workgroup of the assignment-mode kernel
 constexpr int assign_points_per_wg(int low, int DP) { return pipe_points_per_wg(low, DP); }
-constexpr int kDirectPointsPerWg = 64;
+constexpr int kDirectPointsPerWg = 128;
 // small-problem assignment kernel (d <= 32, k <= 64): four waves, each
 // sweeping `gpw` groups of 32 points
 constexpr int kSmallWaves = 4;
