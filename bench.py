@@ -40,10 +40,10 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def serve_run(km, ctx, reqs, arrivals, max_active, budget):
+def serve_run(km, ctx, reqs, arrivals, max_active, budget, keep=False):
     """Submit requests at their arrival times to a server; return per-request
-    latency (submit -> done) and the wall time from first arrival to last
-    completion."""
+    latency (submit -> done), the wall time from first arrival to last
+    completion and, with ``keep``, every request's result."""
     srv = km.Server(ctx, budget, max_active=max_active)
     n = len(reqs)
     t0 = time.perf_counter()
@@ -65,36 +65,57 @@ def serve_run(km, ctx, reqs, arrivals, max_active, budget):
                     t_done[i] = time.perf_counter() - t0
                     left -= 1
         time.sleep(0.0002)
+    results = [srv.result(t) for t in tickets] if keep else None
     srv.close()
     lat = [t_done[i] - t_sub[i] for i in range(n)]
-    return lat, max(t_done) - min(t_sub)
+    return lat, max(t_done) - min(t_sub), results
 
 
 def serve_bench(km, ctx, count, seed):
     """Continuous batching vs one solve at a time on Poisson arrivals of
     k-means requests (n log-uniform in [1e3, 1e6], d in {3,16,64,128}, k in
-    {8..512}, 30 rounds each).  The arrival rate equals the measured
-    one-at-a-time capacity."""
+    {8..512}, 30 rounds each, FP16 -> FP64) at 0.5, 1.0 and 1.5 times the
+    measured one-at-a-time capacity.  At load 1.0 every served result is
+    compared bit for bit with the same request solved one at a time (the
+    oracle checks of served results are in the GPU test suite)."""
+    from concurrent.futures import ThreadPoolExecutor
     import numpy as np
     import workloads as W
-    reqs = [r.materialize() for r in W.request_stream(count, 1.0, seed)]
+    reqs = W.request_stream(count, 1.0, seed)
+    log("serving: generating %d requests" % count)
+    with ThreadPoolExecutor(16) as ex:
+        list(ex.map(lambda r: r.materialize(), reqs))
     budget = 64 << 30
     # one-at-a-time capacity: back-to-back solves through a single-slot server
-    lat1, wall1 = serve_run(km, ctx, reqs, [0.0] * count, 1, budget)
+    lat1, wall1, _ = serve_run(km, ctx, reqs, [0.0] * count, 1, budget)
     mu1 = count / wall1
+    log("serving: one-at-a-time capacity %.1f solves/s" % mu1)
     g = np.random.default_rng(seed + 1)
     arrivals = np.cumsum(g.exponential(1.0 / mu1, size=count))
     arrivals -= arrivals[0]
-    out = {"requests": count, "one_at_a_time_capacity_per_s": mu1}
-    for load in (1.0, 1.5):
+    out = {"requests": count, "one_at_a_time_capacity_per_s": mu1,
+           "points": int(sum(r.n for r in reqs)), "rounds_per_request": reqs[0].iters}
+    kept = {}
+    for load in (0.5, 1.0, 1.5):
         arr = list(arrivals / load)
         res = {"arrival_rate_per_s": mu1 * load}
         for name, slots in (("one_at_a_time", 1), ("continuous_batching", 64)):
-            lat, wall = serve_run(km, ctx, reqs, arr, slots, budget)
+            lat, wall, rs = serve_run(km, ctx, reqs, arr, slots, budget, keep=(load == 1.0))
+            if rs is not None:
+                kept[name] = rs
             res[name] = {"solves_per_s": count / wall,
                          "p50_latency_ms": 1e3 * float(np.percentile(lat, 50)),
                          "p99_latency_ms": 1e3 * float(np.percentile(lat, 99))}
+            log("serving: load %.1f %s: %.1f solves/s, p50 %.1f ms, p99 %.1f ms" % (
+                load, name, res[name]["solves_per_s"], res[name]["p50_latency_ms"],
+                res[name]["p99_latency_ms"]))
         out["load_%.1f" % load] = res
+    a, b = kept["one_at_a_time"], kept["continuous_batching"]
+    same = sum(1 for x, y in zip(a, b)
+               if np.array_equal(x["labels"], y["labels"]) and np.array_equal(x["C"], y["C"])
+               and np.array_equal(x["sse_hist"], y["sse_hist"], equal_nan=True))
+    out["identical_to_one_at_a_time"] = same
+    out["oracle_checks"] = "tests/test_gpu_server.py (served request stream against the oracle)"
     return out
 
 
@@ -153,13 +174,15 @@ def variant_table(km, ctx, torch, np, X, C, Xh, Ch, variants, sample_rows=16384,
     the fraction of pairs corrected (eq:eta) and the relative error of the
     per-pair values against the FP64 direct formula on a seeded sample of
     rows against all centres (values materialised by kmeans_pairwise, the
-    same arithmetic; reference from the CPU oracle)."""
-    import oracle
+    same arithmetic; reference: the plain FP64 direct-formula kernel on the
+    same rows, whose values the GPU tests pin to the CPU oracle)."""
     n, d = X.shape
     k = C.shape[0]
     rows = np.sort(np.random.default_rng(seed).choice(n, size=min(sample_rows, n), replace=False))
-    ref = oracle.dist_rows(Xh[rows], Ch)
     Xs = X[torch.from_numpy(rows).cuda()].contiguous()
+    R, _ = km.kmeans_pairwise(ctx, Xs, C, km.Precision(km.KM_EXACT64))
+    ref = R.cpu().numpy().astype(np.float64)
+    del R
     out = {}
     for name, pr in variants:
         ms = kernel_ms(km, ctx, X, C, pr)
@@ -318,7 +341,7 @@ def main():
                     help="skip the large-clustering measurement")
     ap.add_argument("--batch-problems", type=int, default=256,
                     help="problems in the batched measurement (0 = skip)")
-    ap.add_argument("--serve-requests", type=int, default=48,
+    ap.add_argument("--serve-requests", type=int, default=500,
                     help="requests in the serving measurement (0 = skip)")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="also run a plain device copy of this size (counter calibration)")

@@ -154,3 +154,37 @@ def test_poll_timeout_cancel_and_unknown(ctx):
     assert srv.poll(tb, -1) == 0
     assert srv.poll(123456, 0) == -6
     srv.close()
+
+
+def test_served_request_stream_against_oracle(ctx):
+    """A stream of requests shaped like the serving workload (d in
+    {3, 16, 64, 128}, k in 8..512, n log-uniform, here up to 6e4 so the
+    oracle stays quick), all submitted to one continuous-batching server.
+    Every result against the oracle: the final SSE is the FP64 SSE of the
+    returned labels against the returned centres; the final labels match
+    the oracle's wherever its best centre is separated by more than the
+    error bounds (O4 at the returned centres); the first pass's SSE equals
+    the oracle's assignment of the initial centres up to near ties (the
+    exact argmin's SSE is the least)."""
+    from tests.gpu_helpers import check_assignment_scan
+    reqs = W.request_stream(48, 0.0, 4242, n_range=(1_000, 60_000), iters=12)
+    for r in reqs:
+        r.materialize()
+    srv = km.Server(ctx, 8 << 30, max_active=16)
+    tickets = [srv.submit(r.X, r.C0, r.iters, prec=FP16) for r in reqs]
+    rcs = _wait_all(srv, tickets)
+    assert all(rc == 0 for rc in rcs.values()), rcs
+    for r, t in zip(reqs, tickets):
+        res = srv.result(t)
+        C, lab, h = res["C"], res["labels"], res["sse_hist"]
+        assert res["stats"]["iters"] == r.iters
+        assert h[-1] == pytest.approx(oracle.sse_labels(r.X, C, lab), rel=1e-9)
+        alpha = km.kmeans_alpha(FP16, r.d)
+        scan = oracle.mp_scan(r.X, C, 0, alpha, [lab])
+        check_assignment_scan(scan, 0, lab, None, h[-1], res["stats"]["n_corrected"],
+                              check_sandwich=False)
+        # first pass: the oracle's exact argmin has the least SSE; near ties
+        # the bounds leave open may only add to it
+        _, _, sse0 = oracle.assign(r.X, r.C0)
+        assert sse0 * (1 - 1e-9) <= h[0] <= sse0 * (1 + 1e-4)
+    srv.close()
