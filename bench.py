@@ -321,7 +321,10 @@ def batch_bench(km, ctx, torch, W, np, count=256, iters=30):
            "batched_solves_per_s": count / tb, "one_by_one_solves_per_s": count / ts,
            "labels_identical": same,
            "batched_assign_bytes_GBps": alg_bytes / tb / 1e9,
-           "batched_frac_of_hbm_peak": alg_bytes / tb / 1e9 / HBM_PEAK_GBS}
+           "batched_frac_of_hbm_peak": alg_bytes / tb / 1e9 / HBM_PEAK_GBS,
+           # the sweep-length tuner's choice for this launch (made by the
+           # first, untimed batched solve and reused by the timed one)
+           "tuner_cache": km.kmeans_tune_dump(ctx).strip()}
     log("batched: %.1f ms batched, %.1f ms one by one, labels identical %s" %
         (1e3 * tb, 1e3 * ts, same))
     return out

@@ -23,7 +23,7 @@ __all__ = [
     "kmeans_lloyd", "kmeans_solve_batch", "kmeans_pairwise", "kmeans_quantize",
     "kmeans_alpha", "kmeans_status_string", "Server", "kmeans_server_create",
     "kmeans_submit", "kmeans_poll", "kmeans_cancel", "kmeans_server_destroy",
-    "kmeans_timing_enable", "kmeans_timing_read",
+    "kmeans_timing_enable", "kmeans_timing_read", "kmeans_tune_cache", "kmeans_tune_dump",
 ]
 
 KM_LOW_FP16, KM_LOW_BF16, KM_LOW_FP32, KM_EXACT64 = 0, 1, 2, 3
@@ -115,11 +115,14 @@ def lib():
                 "kmeans_server_destroy": [P],
                 "kmeans_timing_enable": [P, i32],
                 "kmeans_timing_read": [P, ct.POINTER(ct.c_float), i32, ct.POINTER(i32)],
+                "kmeans_tune_cache": [P, ct.c_char_p],
             }
             for name, args in sig.items():
                 fn = getattr(L, name)
                 fn.argtypes = args
                 fn.restype = i32
+            L.kmeans_tune_dump.argtypes = [P, ct.c_char_p, ct.c_int64]
+            L.kmeans_tune_dump.restype = ct.c_int64
             L.kmeans_status_string.argtypes = [i32]
             L.kmeans_status_string.restype = ct.c_char_p
             _lib = L
@@ -216,6 +219,24 @@ def kmeans_context_create(device: int = 0) -> Context:
 def kmeans_timing_enable(ctx: Context, enable: bool = True) -> None:
     _check(lib().kmeans_timing_enable(ctx.handle, 1 if enable else 0),
            "kmeans_timing_enable")
+
+
+def kmeans_tune_cache(ctx: Context, path):
+    """Make the context's tuning choices persistent in ``path`` (None: memory
+    only)."""
+    p = None if path is None else os.fsencode(path)
+    _check(lib().kmeans_tune_cache(ctx.handle, p), "kmeans_tune_cache")
+
+
+def kmeans_tune_dump(ctx: Context) -> str:
+    """The context's tuning choices, one line per shape bucket: key, groups
+    of 32 points per wave, the timed candidates in ms."""
+    n = lib().kmeans_tune_dump(ctx.handle, None, 0)
+    if n < 0:
+        raise KMeansError(int(n), "kmeans_tune_dump")
+    buf = ct.create_string_buffer(int(n) + 1)
+    lib().kmeans_tune_dump(ctx.handle, buf, int(n) + 1)
+    return buf.value.decode()
 
 
 def kmeans_timing_read(ctx: Context, max_count: int = 4096):

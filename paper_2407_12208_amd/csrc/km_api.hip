@@ -1080,23 +1080,40 @@ extern "C" int32_t kmeans_solve_batch(km_context* ctx, km_problem* probs, int32_
   bool need_tol = false;
   for (int i = 0; i < count; ++i) need_tol |= probs[i].tol > 0.0;
   // Sweep-length tuner of the small-problem launches: the first rounds run
-  // with 2, 4 and 8 groups per wave (timed with events around the
+  // with 2, 4, 8 and 16 groups per wave (never fewer than a problem's own,
+  // whose partials bound the workspace; timed with events around the
   // assignment launches) and the fastest is kept for the rest.  These are
   // real rounds: labels and counts do not depend on the partition and the
   // rounds' SSE comes from the update, so results are the same whatever is
   // chosen (the final pass uses each problem's own partition).
-  static const int kTuneGpw[3] = {2, 4, 8};
+  // A choice made before for the same shape bucket (the context's tuning
+  // cache, persisted when the caller gave it a file) is used without tuning.
+  static constexpr int kTuneN = 4;
+  static const int kTuneGpw[kTuneN] = {2, 4, 8, 16};
   bool tune = false;
+  std::string tune_key;
+  int cached_gpw = 0;
   {
     // every problem active through the tuning rounds, so that each round
     // times the same launches
     int64_t small_pts = 0;
-    int min_iter = INT32_MAX;
+    int min_iter = INT32_MAX, xd = 0, k_pad = 0;
+    bool fallback = false;
     for (auto& s : S) {
-      if (s.plan.xd > 0) small_pts += s.prob->n;
+      if (s.plan.xd > 0) {
+        small_pts += s.prob->n;
+        xd = std::max(xd, s.plan.xd);
+        k_pad = std::max(k_pad, s.plan.k_pad);
+        fallback |= s.plan.route == Route::Mfma;
+      }
       min_iter = std::min(min_iter, (int)s.prob->max_iter);
     }
-    tune = !ctx->timing && !need_tol && small_pts >= 2 * (int64_t)kSmallWaves * 32 * 4096 && min_iter >= 4;
+    if (small_pts > 0) {
+      tune_key = TuneCache::key(p.low, p.high, fallback, xd, k_pad, small_pts);
+      if (!ctx->tune.lookup(tune_key, &cached_gpw)) cached_gpw = 0;
+    }
+    tune = cached_gpw == 0 && !ctx->timing && !need_tol &&
+           small_pts >= 2 * (int64_t)kSmallWaves * 32 * 4096 && min_iter >= kTuneN + 1;
   }
   auto apply_gpw = [&](int g) {
     for (auto& s : S)
@@ -1107,7 +1124,7 @@ extern "C" int32_t kmeans_solve_batch(km_context* ctx, km_problem* probs, int32_
       }
   };
   int round = 0;
-  int ev_mark[4] = {0, 0, 0, 0};
+  int ev_mark[kTuneN + 1] = {};
   // the tuner borrows the context's launch timing; it is off again however
   // this call returns
   struct TimingOff {
@@ -1124,31 +1141,35 @@ extern "C" int32_t kmeans_solve_batch(km_context* ctx, km_problem* probs, int32_
     ctx->timing = true;
     ctx->ev_used = 0;
   }
+  if (cached_gpw > 0) apply_gpw(cached_gpw);
   for (;;) {
     std::vector<BatchState*> act;
     for (auto& s : S)
       if (!s.done) act.push_back(&s);
     if (act.empty()) break;
-    if (tune && round < 3) apply_gpw(kTuneGpw[round]);
+    if (tune && round < kTuneN) apply_gpw(kTuneGpw[round]);
     KM_HIP(enqueue_batch_round(ctx, act, st));
-    if (tune && round < 3) ev_mark[round + 1] = ctx->ev_used;
-    if (tune && round == 2) {
-      KM_HIP(hipEventSynchronize(ctx->timing_event(2 * ev_mark[3] - 1)));
+    if (tune && round < kTuneN) ev_mark[round + 1] = ctx->ev_used;
+    if (tune && round == kTuneN - 1) {
+      KM_HIP(hipEventSynchronize(ctx->timing_event(2 * ev_mark[kTuneN] - 1)));
       int best = 0;
       float best_ms = 0.0f;
-      for (int r = 0; r < 3; ++r) {
+      std::vector<float> times;
+      for (int r = 0; r < kTuneN; ++r) {
         float tot = 0.0f;
         for (int e = ev_mark[r]; e < ev_mark[r + 1]; ++e) {
           float ms = 0.0f;
           KM_HIP(hipEventElapsedTime(&ms, ctx->timing_event(2 * e), ctx->timing_event(2 * e + 1)));
           tot += ms;
         }
+        times.push_back(tot);
         if (r == 0 || tot < best_ms) {
           best = r;
           best_ms = tot;
         }
       }
       apply_gpw(kTuneGpw[best]);
+      ctx->tune.store(tune_key, kTuneGpw[best], times);
       ctx->timing = false;
       ctx->ev_used = 0;
       tune = false;

@@ -6,7 +6,9 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <map>
 #include <mutex>
+#include <string>
 #include <vector>
 
 #include "../../include/kmeans.h"
@@ -69,6 +71,25 @@ struct Uploader {
   void* put(const void* src, size_t bytes, hipStream_t st);
 };
 
+// Persisted choices of the sweep-length tuner (km_tune.cpp).
+struct TuneCache {
+  struct Entry {
+    int gpw;
+    std::vector<float> ms;
+  };
+  std::mutex mu;
+  std::map<std::string, Entry> entries;
+  std::string path;
+  static std::string key(int low, int high, bool fallback, int xd, int k_pad, int64_t points);
+  bool lookup(const std::string& k, int* gpw);
+  void store(const std::string& k, int gpw, const std::vector<float>& ms);
+  int32_t set_path(const char* p);
+  std::string dump();
+
+ private:
+  void save_locked();
+};
+
 struct km_context_impl {
   int device = 0;
   int num_cu = 0;
@@ -85,6 +106,7 @@ struct km_context_impl {
   hipEvent_t ws_event = nullptr;
   hipStream_t ws_stream = nullptr;
   bool ws_valid = false;
+  TuneCache tune;
   // kernel timing
   bool timing = false;
   std::vector<hipEvent_t> ev_pool;  // pairs: [2i] start, [2i+1] stop

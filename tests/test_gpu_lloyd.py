@@ -305,3 +305,45 @@ def test_batch_equals_alone_when_the_launch_sweeps_longer(ctx):
         np.testing.assert_array_equal(host(items[i].mindist), host(mind))
         np.testing.assert_array_equal(host(items[i].sse_hist), host(sse_hist))
         assert stats[i]["n_corrected"] == st["n_corrected"]
+
+
+def test_batch_tuner_choice_is_cached_persisted_and_harmless(ctx, tmp_path):
+    # eight segmentation-shaped problems (2.6 M points in one small-problem
+    # launch): the first batched solve times 2, 4, 8 and 16 groups per wave and
+    # records the fastest for the launch's shape bucket; a second solve of
+    # the same bucket, in a new context reading the persisted file, uses the
+    # choice without timing; the results are bitwise the same either way
+    insts = W.segmentation_batch(8, 77, hw_range=(512, 640))
+    assert sum(b["X"].shape[0] for b in insts) >= 2 * 4 * 32 * 4096
+    path = str(tmp_path / "tune.txt")
+
+    def solve(c):
+        items = [km.BatchItem(X=dev(b["X"]), C=dev(b["C0"]), max_iter=6) for b in insts]
+        km.kmeans_solve_batch(c, items, FP16)
+        return [(host(it.labels), host(it.C)) for it in items]
+
+    c1 = km.Context(0)
+    km.kmeans_tune_cache(c1, path)
+    r1 = solve(c1)
+    text = km.kmeans_tune_dump(c1)
+    lines = [l for l in text.splitlines() if l.strip()]
+    assert len(lines) == 1 and lines[0].startswith("small:low=0:high=0:fb=1:xd=8:")
+    gpw = int(lines[0].split()[1])
+    assert gpw in (2, 4, 8, 16) and len(lines[0].split()) == 6
+    with open(path) as f:
+        assert f.read() == text
+    c1.close()
+    c2 = km.Context(0)
+    km.kmeans_tune_cache(c2, path)
+    assert km.kmeans_tune_dump(c2) == text
+    r2 = solve(c2)
+    assert km.kmeans_tune_dump(c2) == text  # nothing re-timed
+    c2.close()
+    # a context without the cache tunes again (its own timing may choose
+    # another partition): the same bits
+    r3 = solve(ctx)
+    for (l1, c1_), (l2, c2_), (l3, c3_) in zip(r1, r2, r3):
+        np.testing.assert_array_equal(l1, l2)
+        np.testing.assert_array_equal(l1, l3)
+        np.testing.assert_array_equal(c1_, c2_)
+        np.testing.assert_array_equal(c1_, c3_)
