@@ -269,6 +269,25 @@ def large_bench(km, ctx, torch, W, np):
                      "final_sse": float(hist[-1].item())}
         log("large %s: %.3f ms per round, eta %.3g" % (name, out[name]["ms_per_round"],
                                                          out[name]["eta"]))
+    # precision schedule: uniform FP16 while a round lowers the SSE by at
+    # least 1e-3 of it (at most 40 rounds), then FP16 -> FP64
+    C = torch.from_numpy(C0).cuda()
+    uni = km.Precision(km.KM_LOW_FP16, km.KM_ALPHA_NONE)
+    late = km.Precision(km.KM_LOW_FP16)
+    km.kmeans_lloyd_schedule(ctx, Xd, C, 1, uni, late, 1e-3, 40, stats=False, sync=True)
+    C.copy_(torch.from_numpy(C0).cuda())
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, _, _, hist, st, sw = km.kmeans_lloyd_schedule(ctx, Xd, C, iters, uni, late, 1e-3, 40,
+                                                     sse_hist=True, stats=True, sync=True)
+    dt = time.perf_counter() - t0
+    out["fp16_schedule"] = {"rounds_per_s": iters / dt, "ms_per_round": 1e3 * dt / (iters + 1),
+                            "eta": st["n_corrected"] / max(st["n_pairs"], 1),
+                            "final_sse": float(hist[-1].item()), "switch_round": sw,
+                            "rule": "uniform FP16 while the round's SSE falls by >= 1e-3 of it "
+                                    "(<= 40 rounds), then FP16 -> FP64"}
+    log("large fp16_schedule: %.3f ms per round, switch at round %d" % (
+        out["fp16_schedule"]["ms_per_round"], sw))
     out["speedup_fp16_fp64_vs_fp64_direct"] = (out["fp16_fp64"]["rounds_per_s"] /
                                                out["fp64_direct"]["rounds_per_s"])
     out["speedup_bf16_hw_alpha_vs_fp64_direct"] = (out["bf16_fp64_hw_alpha"]["rounds_per_s"] /

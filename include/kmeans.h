@@ -240,6 +240,30 @@ int32_t kmeans_lloyd(km_context *ctx, const float *X, int64_t n, int32_t d,
                      double *sse_hist, km_stats *stats, void *stream,
                      uint32_t flags);
 
+/* ---- Lloyd's algorithm with a precision schedule ---------------------------
+ * The precision guidance of Section 6 (closing implications paragraph):
+ * while centre-point distances are large, uniform low precision suffices;
+ * near convergence, cancellation calls for the fallback.  The paper gives no
+ * switching criterion; this entry point uses one the host loop can check
+ * each round: rounds use `early` while the round's SSE falls by at least the
+ * fraction switch_rel of the previous round's SSE, for at most max_early
+ * rounds; every later round and the final pass use `late`.  With
+ * max_early = 0 it is kmeans_lloyd with `late`.  Each early round costs one
+ * device-to-host read (the round's SSE and shift).  *switch_round (host,
+ * nullable) receives the index of the first round in `late` (the number of
+ * rounds if the final pass is the first).  stats sums the corrected pairs of
+ * both phases; sse_last is the final pass's.  Other arguments as
+ * kmeans_lloyd. */
+int32_t kmeans_lloyd_schedule(km_context *ctx, const float *X, int64_t n,
+                              int32_t d, int32_t k, float *C_inout,
+                              int32_t max_iter, double tol,
+                              const km_precision *early,
+                              const km_precision *late, double switch_rel,
+                              int32_t max_early, int32_t *labels,
+                              float *mindist, double *sse_hist,
+                              km_stats *stats, int32_t *switch_round,
+                              void *stream, uint32_t flags);
+
 /* ---- many independent problems in one set of launches ----------------------
  * Solves count problems (device pointers) with the same precision.  Each
  * phase of a Lloyd round is one launch over a work list that spans all

@@ -20,7 +20,7 @@ __all__ = [
     "KM_HIGH_FP64", "KM_HIGH_FP32", "KM_HIGH_LOW",
     "KM_SYNC", "KMeansError", "Precision", "Stats", "Problem", "library_path", "lib",
     "Context", "kmeans_context_create", "kmeans_assign", "kmeans_assign_static", "kmeans_update",
-    "kmeans_lloyd", "kmeans_solve_batch", "kmeans_pairwise", "kmeans_quantize",
+    "kmeans_lloyd", "kmeans_lloyd_schedule", "kmeans_solve_batch", "kmeans_pairwise", "kmeans_quantize",
     "kmeans_alpha", "kmeans_status_string", "Server", "kmeans_server_create",
     "kmeans_submit", "kmeans_poll", "kmeans_cancel", "kmeans_server_destroy",
     "kmeans_timing_enable", "kmeans_timing_read", "kmeans_tune_cache", "kmeans_tune_dump",
@@ -104,6 +104,8 @@ def lib():
                 "kmeans_assign_static": [P, P, i64, i32, P, i32, PP, P, P, P, PS, P, u32],
                 "kmeans_update": [P, P, i64, i32, P, i32, P, P, P, P, P, P, u32],
                 "kmeans_lloyd": [P, P, i64, i32, i32, P, i32, dbl, PP, P, P, P, PS, P, u32],
+                "kmeans_lloyd_schedule": [P, P, i64, i32, i32, P, i32, dbl, PP, PP, dbl, i32, P, P, P, PS,
+                                          ct.POINTER(i32), P, u32],
                 "kmeans_solve_batch": [P, ct.POINTER(Problem), i32, PP, P, u32],
                 "kmeans_pairwise": [P, P, i64, i32, P, i32, PP, P, P, P, u32],
                 "kmeans_quantize": [P, P, i64, i32, P, P, u32],
@@ -386,6 +388,39 @@ def kmeans_lloyd(ctx: Context, X, C_inout, max_iter: int, tol: float = 0.0,
         KM_SYNC if sync else 0)
     _check(code, "kmeans_lloyd")
     return C_inout, labels, mindist, sse_hist, (st.as_dict() if st is not None else None)
+
+
+def kmeans_lloyd_schedule(ctx: Context, X, C_inout, max_iter: int, early, late,
+                          switch_rel: float, max_early: int, tol: float = 0.0, labels=None,
+                          mindist=None, sse_hist=None, stats=True, stream=None, sync=False):
+    """Lloyd's algorithm with the precision schedule of kmeans_lloyd_schedule
+    (``early`` while the round's relative SSE decrease is >= ``switch_rel``,
+    at most ``max_early`` rounds, then ``late``).  Returns ``(C_inout, labels,
+    mindist, sse_hist, stats, switch_round)``."""
+    torch = _torch()
+    n, d = X.shape
+    k = C_inout.shape[0]
+    if labels is None:
+        labels = torch.empty(n, dtype=torch.int32, device=X.device)
+    if mindist is True:
+        mindist = torch.empty(n, dtype=torch.float32, device=X.device)
+    if sse_hist is True:
+        sse_hist = torch.full((max_iter + 1,), float("nan"), dtype=torch.float64,
+                              device=X.device)
+    st = Stats() if stats else None
+    sw = ct.c_int32(-1)
+    code = lib().kmeans_lloyd_schedule(
+        ctx.handle, _dev_ptr(X, torch.float32, "X", n * d), n, d, k,
+        _dev_ptr(C_inout, torch.float32, "C_inout", k * d), int(max_iter), float(tol),
+        _prec(early), _prec(late), float(switch_rel), int(max_early),
+        _dev_ptr(labels, torch.int32, "labels", n),
+        _dev_ptr(mindist, torch.float32, "mindist", n, allow_none=True),
+        _dev_ptr(sse_hist, torch.float64, "sse_hist", max_iter + 1, allow_none=True),
+        ct.byref(st) if st is not None else None, ct.byref(sw), _stream_ptr(stream),
+        KM_SYNC if sync else 0)
+    _check(code, "kmeans_lloyd_schedule")
+    return (C_inout, labels, mindist, sse_hist, (st.as_dict() if st is not None else None),
+            sw.value)
 
 
 @dataclass

@@ -901,6 +901,106 @@ int32_t kmeans_lloyd(km_context* ctx, const float* X, int64_t n, int32_t d, int3
   return KM_OK;
 }
 
+int32_t kmeans_lloyd_schedule(km_context* ctx, const float* X, int64_t n, int32_t d, int32_t k, float* C_inout,
+                              int32_t max_iter, double tol, const km_precision* early, const km_precision* late,
+                              double switch_rel, int32_t max_early, int32_t* labels, float* mindist,
+                              double* sse_hist, km_stats* stats, int32_t* switch_round, void* stream,
+                              uint32_t flags) {
+  if (!ctx || !X || !C_inout || !labels || max_iter < 0 || max_early < 0 || !(switch_rel >= 0.0))
+    return KM_ERR_ARG;
+  const km_precision pe = precision_or_default(early), pl_ = precision_or_default(late);
+  int32_t v = validate_precision(pe);
+  if (v == KM_OK) v = validate_precision(pl_);
+  if (v == KM_OK) v = check_shape(n, d, k, pe);
+  if (v == KM_OK) v = check_shape(n, d, k, pl_);
+  if (v != KM_OK) return v;
+  hipStream_t st = (hipStream_t)stream;
+  KM_HIP(hipSetDevice(ctx->device));
+  WorkspaceUse ws_use(ctx, st);
+  KM_HIP(ws_use.err);
+  AssignPlan ae = plan_assign(pe, n, d, k), al = plan_assign(pl_, n, d, k);
+  Plan pl;
+  plan_pass(pl, ae);
+  plan_pass(pl, al);
+  plan_update(pl, n, d, k);
+  pl.add<float>((size_t)k * d);           // second centre buffer
+  pl.add<double>((size_t)max_iter + 1);   // round SSEs when the caller keeps none
+  KM_HIP(ctx->arena.ensure(pl.bytes));
+  ctx->arena.reset();
+  PassBufs be = carve_pass(ctx->arena, ae), bl = carve_pass(ctx->arena, al);
+  UpdateProb u = carve_update(ctx->arena, n, d, k);
+  float* Cw = ctx->arena.take<float>((size_t)k * d);
+  double* sse_dev = sse_hist ? sse_hist : ctx->arena.take<double>((size_t)max_iter + 1);
+  KM_HIP(zero_status_result(be.status, be.result, st));
+  KM_HIP(zero_status_result(bl.status, bl.result, st));
+  u.X = X;
+  u.labels = labels;
+  float* cur = C_inout;
+  float* nxt = Cw;
+  // early rounds: the early precision while the round's relative SSE
+  // decrease is at least switch_rel (and at most max_early rounds); then the
+  // late precision for the remaining rounds and the final pass
+  bool late_on = max_early == 0;
+  int32_t switched = late_on ? 0 : -1;
+  double prev_sse = 0.0;
+  int32_t it = 0;
+  for (; it < max_iter; ++it) {
+    const AssignPlan& a = late_on ? al : ae;
+    const PassBufs& b = late_on ? bl : be;
+    KM_HIP(enqueue_pass(ctx, a, b, X, n, d, cur, k, labels, nullptr, nullptr, 0, nullptr, nullptr, false,
+                        it > 0, st));
+    u.C_old = cur;
+    u.C_new = nxt;
+    u.sse_out = sse_dev + it;
+    u.result = b.result;
+    u.status = b.status;
+    KM_HIP(run_update(ctx, {u}, st));
+    std::swap(cur, nxt);
+    if (!late_on || tol > 0.0) {
+      KM_HIP(hipMemcpyAsync(ctx->h_scalar, &b.result->shift, sizeof(double), hipMemcpyDeviceToHost, st));
+      KM_HIP(hipMemcpyAsync(ctx->h_scalar + 1, sse_dev + it, sizeof(double), hipMemcpyDeviceToHost, st));
+      KM_HIP(hipStreamSynchronize(st));
+      const double shift = ctx->h_scalar[0], sse_t = ctx->h_scalar[1];
+      if (!late_on) {
+        const bool flat = it > 0 && !(prev_sse - sse_t >= switch_rel * prev_sse);
+        if (flat || it + 1 >= max_early) {
+          late_on = true;
+          switched = it + 1;
+        }
+        prev_sse = sse_t;
+      }
+      if (tol > 0.0 && shift < tol) {
+        ++it;
+        break;
+      }
+    }
+  }
+  if (switched < 0) switched = it;  // the final pass is the first in the late precision
+  if (switch_round) *switch_round = switched;
+  KM_HIP(enqueue_pass(ctx, al, bl, X, n, d, cur, k, labels, mindist, sse_hist ? sse_hist + it : nullptr, 0,
+                      nullptr, nullptr, true, it > 0, st));
+  if (cur != C_inout)
+    KM_HIP(hipMemcpyAsync(C_inout, cur, sizeof(float) * (size_t)k * d, hipMemcpyDeviceToDevice, st));
+  if (!stats && !(flags & KM_SYNC)) return KM_OK;
+  KM_HIP(hipMemcpyAsync(ctx->h_result, be.result, sizeof(KResult), hipMemcpyDeviceToHost, st));
+  KM_HIP(hipMemcpyAsync(ctx->h_result + 1, bl.result, sizeof(KResult), hipMemcpyDeviceToHost, st));
+  KM_HIP(hipStreamSynchronize(st));
+  const KResult re = ctx->h_result[0], rl = ctx->h_result[1];
+  const int32_t ds_e = status_from_bits(re.status), ds_l = status_from_bits(rl.status);
+  const int32_t ds = ds_e != KM_OK ? ds_e : ds_l;
+  if (stats) {
+    stats->n_corrected = (ae.route == Route::Direct64Exact ? 0 : re.n_corrected) +
+                         (al.route == Route::Direct64Exact ? 0 : rl.n_corrected);
+    stats->n_pairs = re.n_pairs + rl.n_pairs;
+    stats->iters = it;
+    stats->data_status = ds;
+    stats->sse_last = rl.sse;
+    stats->shift_last = switched < it ? rl.shift : re.shift;
+    stats->alpha_used = al.alpha_used;
+  }
+  return ds;
+}
+
 }  // extern "C"
 
 // ---------------------------------------------------------------------------

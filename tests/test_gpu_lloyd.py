@@ -347,3 +347,48 @@ def test_batch_tuner_choice_is_cached_persisted_and_harmless(ctx, tmp_path):
         np.testing.assert_array_equal(l1, l3)
         np.testing.assert_array_equal(c1_, c2_)
         np.testing.assert_array_equal(c1_, c3_)
+
+
+# ---------------------------------------------------------------------------
+# precision schedule (uniform low precision early, fallback near convergence)
+# ---------------------------------------------------------------------------
+
+UNIFORM16 = km.Precision(km.KM_LOW_FP16, km.KM_ALPHA_NONE)
+
+
+@pytest.mark.parametrize("switch_rel,max_early", [(1e-2, 30), (0.0, 5), (1e-3, 0), (1.0, 30)])
+def test_schedule_equals_the_two_phases_and_obeys_its_rule(ctx, switch_rel, max_early):
+    X, _, _ = W.blobs(60_000, 16, 24, seed=31)
+    C0 = W.init_centroids(X, 24, 32)
+    iters = 25
+    Xd = dev(X)
+    C = dev(C0)
+    _, lab, md, h, st, sw = km.kmeans_lloyd_schedule(ctx, Xd, C, iters, UNIFORM16, FP16, switch_rel,
+                                                     max_early, mindist=True, sse_hist=True)
+    h = host(h)
+    assert 0 <= sw <= iters
+    # the rule on the returned SSEs: rounds 0 .. sw-1 ran early; each of
+    # rounds 1 .. sw-2 fell by at least switch_rel, and round sw-1 either did
+    # not (a flat round ends the early phase) or reached the cap
+    for t in range(1, sw - 1):
+        assert h[t - 1] - h[t] >= switch_rel * h[t - 1]
+    if 0 < sw < iters:
+        capped = sw == max_early
+        flat = sw >= 2 and not (h[sw - 2] - h[sw - 1] >= switch_rel * h[sw - 2])
+        assert capped or flat
+    if max_early == 0:
+        assert sw == 0
+    # the same as the early precision for sw rounds, then the late one
+    Ca = dev(C0)
+    _, _, _, ha, _ = km.kmeans_lloyd(ctx, Xd, Ca, sw, prec=UNIFORM16, sse_hist=True)
+    Cb = Ca.clone()
+    _, lb, mb, hb, _ = km.kmeans_lloyd(ctx, Xd, Cb, iters - sw, prec=FP16, mindist=True, sse_hist=True)
+    np.testing.assert_array_equal(host(C), host(Cb))
+    np.testing.assert_array_equal(host(lab), host(lb))
+    np.testing.assert_array_equal(host(md), host(mb))
+    np.testing.assert_array_equal(h[:sw], host(ha)[:sw])
+    np.testing.assert_array_equal(h[sw:], host(hb))
+    # the final assignment against the oracle at the returned centres
+    fmt_alpha = km.kmeans_alpha(FP16, 16)
+    from tests.gpu_helpers import check_assignment
+    check_assignment(X, host(C), 0, fmt_alpha, host(lab), host(md), h[-1], None)
