@@ -346,6 +346,30 @@ def batch_bench(km, ctx, torch, W, np, count=256, iters=30):
            "tuner_cache": km.kmeans_tune_dump(ctx).strip()}
     log("batched: %.1f ms batched, %.1f ms one by one, labels identical %s" %
         (1e3 * tb, 1e3 * ts, same))
+    # segmentation fidelity (the paper's Diff): labels of each variant against
+    # the plain FP64 solve of the same instances, after the best one-to-one
+    # matching of cluster ids, on the first 16 instances
+    P = km.Precision
+    m = min(16, count)
+    ref = None
+    fid = {}
+    for name, pr in (("fp64_direct", P(km.KM_EXACT64)), ("fp16_fp64", prec),
+                     ("fp16_uniform", P(km.KM_LOW_FP16, km.KM_ALPHA_NONE)),
+                     ("bf16_uniform", P(km.KM_LOW_BF16, km.KM_ALPHA_NONE)),
+                     ("fp32_uniform", P(km.KM_LOW_FP32, km.KM_ALPHA_NONE))):
+        items = [km.BatchItem(X=X, C=C0.clone(), max_iter=iters) for X, C0 in zip(Xs[:m], C0s[:m])]
+        km.kmeans_solve_batch(ctx, items, pr, with_sse=False)
+        labs = [it.labels.cpu().numpy() for it in items]
+        if ref is None:
+            ref = labs
+            continue
+        diffs = [km.kmeans_label_diff(a, b) for a, b in zip(labs, ref)]
+        fid[name] = {"mean_diff_pct": 100.0 * float(np.mean(diffs)),
+                     "max_diff_pct": 100.0 * float(np.max(diffs))}
+    fid["reference"] = "fp64_direct, %d instances, %d rounds" % (m, iters)
+    out["segmentation_diff_vs_fp64"] = fid
+    log("batched: Diff vs FP64 %s" % {k: round(v["mean_diff_pct"], 3) for k, v in fid.items()
+                                      if isinstance(v, dict)})
     return out
 
 

@@ -264,6 +264,43 @@ int32_t kmeans_lloyd_schedule(km_context *ctx, const float *X, int64_t n,
                               km_stats *stats, int32_t *switch_round,
                               void *stream, uint32_t flags);
 
+/* ---- k-means++ seeding (D^2 weighting) ---------------------------------------
+ * The seeding the paper's introduction names as combinable with the method
+ * (Arthur and Vassilvitskii).  C_out (device, k x d) receives k rows of X:
+ * row 0 is point floor(u_0 n); row i >= 1 is the first point p whose running
+ * sum of weights w, in point order, exceeds u_i * sum(w), where w_p is the
+ * smallest ||x_p - c||^2 over the rows chosen so far (FP64, coordinates in
+ * index order).  The FP64 sums run in a fixed order (per 1024-point block,
+ * then blocks, then the chosen block's points), so the rows depend only on X
+ * and the uniforms.  uniforms: host array of k values in [0, 1) (the random
+ * draws are the caller's).  idx_out (device, k int32, nullable) receives the
+ * chosen point indices.  If every weight is zero (all points coincide with
+ * chosen rows) row i is point floor(u_i n).  1 <= k <= min(n, 65536),
+ * d <= 1024; 2k - 1 launches, one FP64 read of X per row. */
+int32_t kmeans_seed_pp(km_context *ctx, const float *X, int64_t n, int32_t d,
+                       int32_t k, const double *uniforms, float *C_out,
+                       int32_t *idx_out, void *stream, uint32_t flags);
+
+/* ---- clustering agreement (host arrays; no device work) ----------------------
+ * The measures the paper reports next to the SSE (Section 6): labels_a and
+ * labels_b are n int32 labels (any values) of the same points.
+ * kmeans_ari: adjusted Rand index (pair counting, chance-corrected).
+ * kmeans_ami: adjusted mutual information (Vinh, Epps and Bailey), natural
+ *   logarithm, the arithmetic mean of the two entropies as normaliser, the
+ *   expected mutual information under fixed margins.
+ *   Both are 1.0 when both labelings put every point in one cluster or every
+ *   point in its own.
+ * kmeans_label_diff: the segmentation Diff of Section 6.3, the fraction of
+ *   points whose labels differ after the one-to-one matching of cluster ids
+ *   that agrees on the most points (KM_ERR_UNSUPPORTED above 4096 ids).
+ * Each returns KM_OK or KM_ERR_ARG (NULL pointer, n < 1). */
+int32_t kmeans_ari(const int32_t *labels_a, const int32_t *labels_b, int64_t n,
+                   double *ari);
+int32_t kmeans_ami(const int32_t *labels_a, const int32_t *labels_b, int64_t n,
+                   double *ami);
+int32_t kmeans_label_diff(const int32_t *labels_a, const int32_t *labels_b,
+                          int64_t n, double *diff);
+
 /* ---- many independent problems in one set of launches ----------------------
  * Solves count problems (device pointers) with the same precision.  Each
  * phase of a Lloyd round is one launch over a work list that spans all

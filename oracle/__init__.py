@@ -76,6 +76,8 @@ def lib():
             L.oracle_low_fma.argtypes = [dbl, dbl, dbl, i32]
             L.oracle_corr_dist.restype = dbl
             L.oracle_corr_dist.argtypes = [P, P, i32, i32, i32]
+            L.oracle_seed_pp.restype = None
+            L.oracle_seed_pp.argtypes = [P, i64, i32, i32, P, P]
             L.oracle_corr_rows.restype = None
             L.oracle_corr_rows.argtypes = [P, i64, i32, P, i32, i32, i32, P]
             L.oracle_sqdist.restype = dbl
@@ -312,6 +314,17 @@ def corr_rows(X, C, high: int, fmt: int):
     k = C.shape[0]
     out = np.empty((m, k), dtype=np.float64)
     lib().oracle_corr_rows(_ptr(X), m, d, _ptr(C), k, int(high), int(fmt), _ptr(out))
+    return out
+
+
+def seed_pp(X, k: int, uniforms):
+    """O6: indices (int64) of the k-means++ seeds drawn with ``uniforms``."""
+    X = _f32(X)
+    n, d = X.shape
+    u = np.ascontiguousarray(uniforms, dtype=np.float64)
+    assert u.shape == (k,)
+    out = np.empty(k, dtype=np.int64)
+    lib().oracle_seed_pp(_ptr(X), n, d, int(k), _ptr(u), _ptr(out))
     return out
 
 

@@ -49,6 +49,13 @@
  *                   definition (spacing of the binade, ties to even); exact
  *                   results come from exact products and error-free sums in
  *                   FP64.
+ *   O6  seed     -- k-means++ seeding by D^2 weighting (Arthur and
+ *                   Vassilvitskii): the first centre is point floor(u_0 n);
+ *                   each further centre is the first point whose running
+ *                   sum of weights (point order, FP64) exceeds u_i times
+ *                   their total, the weight of a point being its O1
+ *                   squared distance to the nearest centre chosen so far;
+ *                   if every weight is zero, point floor(u_i n).
  *
  * Build: gcc -O2 -ffp-contract=off -fopenmp -shared -fPIC (no fast-math).
  */
@@ -205,6 +212,42 @@ double oracle_corr_dist(const float *x, const float *c, int d, int high, int fmt
     s = oracle_low_fma(t, t, s, f);
   }
   return s;
+}
+
+/* O6: indices of the k seeds; u holds k uniforms in [0, 1). */
+void oracle_seed_pp(const float *X, int64_t n, int d, int k, const double *u, int64_t *idx) {
+  double *w = (double *)malloc(sizeof(double) * (size_t)n);
+  int64_t first = (int64_t)(u[0] * (double)n);
+  idx[0] = first < n ? first : n - 1;
+  for (int i = 1; i < k; ++i) {
+    const float *c = X + idx[i - 1] * (int64_t)d;
+    double total = 0.0;
+    for (int64_t p = 0; p < n; ++p) {
+      double dist = oracle_sqdist(X + p * (int64_t)d, c, d);
+      w[p] = (i == 1 || dist < w[p]) ? dist : w[p];
+      total += w[p];
+    }
+    int64_t pick = -1;
+    if (total > 0.0) {
+      double target = u[i] * total, run = 0.0;
+      int64_t last = -1;
+      for (int64_t p = 0; p < n; ++p) {
+        if (w[p] > 0.0) last = p;
+        run += w[p];
+        if (run > target && w[p] > 0.0) {
+          pick = p;
+          break;
+        }
+      }
+      if (pick < 0) pick = last;
+    }
+    if (pick < 0) {
+      pick = (int64_t)(u[i] * (double)n);
+      if (pick >= n) pick = n - 1;
+    }
+    idx[i] = pick;
+  }
+  free(w);
 }
 
 void oracle_corr_rows(const float *X, int64_t m, int d, const float *C, int k,

@@ -20,7 +20,8 @@ __all__ = [
     "KM_HIGH_FP64", "KM_HIGH_FP32", "KM_HIGH_LOW",
     "KM_SYNC", "KMeansError", "Precision", "Stats", "Problem", "library_path", "lib",
     "Context", "kmeans_context_create", "kmeans_assign", "kmeans_assign_static", "kmeans_update",
-    "kmeans_lloyd", "kmeans_lloyd_schedule", "kmeans_solve_batch", "kmeans_pairwise", "kmeans_quantize",
+    "kmeans_lloyd", "kmeans_lloyd_schedule", "kmeans_seed_pp", "kmeans_ari", "kmeans_ami",
+    "kmeans_label_diff", "kmeans_solve_batch", "kmeans_pairwise", "kmeans_quantize",
     "kmeans_alpha", "kmeans_status_string", "Server", "kmeans_server_create",
     "kmeans_submit", "kmeans_poll", "kmeans_cancel", "kmeans_server_destroy",
     "kmeans_timing_enable", "kmeans_timing_read", "kmeans_tune_cache", "kmeans_tune_dump",
@@ -118,6 +119,10 @@ def lib():
                 "kmeans_timing_enable": [P, i32],
                 "kmeans_timing_read": [P, ct.POINTER(ct.c_float), i32, ct.POINTER(i32)],
                 "kmeans_tune_cache": [P, ct.c_char_p],
+                "kmeans_seed_pp": [P, P, i64, i32, i32, ct.POINTER(dbl), P, P, P, u32],
+                "kmeans_ari": [P, P, i64, ct.POINTER(dbl)],
+                "kmeans_ami": [P, P, i64, ct.POINTER(dbl)],
+                "kmeans_label_diff": [P, P, i64, ct.POINTER(dbl)],
             }
             for name, args in sig.items():
                 fn = getattr(L, name)
@@ -388,6 +393,57 @@ def kmeans_lloyd(ctx: Context, X, C_inout, max_iter: int, tol: float = 0.0,
         KM_SYNC if sync else 0)
     _check(code, "kmeans_lloyd")
     return C_inout, labels, mindist, sse_hist, (st.as_dict() if st is not None else None)
+
+
+def _agreement(fn, name, a, b):
+    import numpy as np
+    a = np.ascontiguousarray(a, dtype=np.int32).ravel()
+    b = np.ascontiguousarray(b, dtype=np.int32).ravel()
+    if a.shape != b.shape:
+        raise ValueError("labelings of different lengths")
+    out = ct.c_double()
+    _check(fn(a.ctypes.data_as(ct.c_void_p), b.ctypes.data_as(ct.c_void_p), a.shape[0],
+              ct.byref(out)), name)
+    return out.value
+
+
+def kmeans_ari(a, b) -> float:
+    """Adjusted Rand index of two host labelings (numpy int arrays)."""
+    return _agreement(lib().kmeans_ari, "kmeans_ari", a, b)
+
+
+def kmeans_ami(a, b) -> float:
+    """Adjusted mutual information (arithmetic normaliser) of two labelings."""
+    return _agreement(lib().kmeans_ami, "kmeans_ami", a, b)
+
+
+def kmeans_label_diff(a, b) -> float:
+    """Fraction of points whose labels differ after the best one-to-one
+    matching of cluster ids (the paper's segmentation Diff)."""
+    return _agreement(lib().kmeans_label_diff, "kmeans_label_diff", a, b)
+
+
+def kmeans_seed_pp(ctx: Context, X, k: int, uniforms, C_out=None, idx_out=None, stream=None,
+                   sync=True):
+    """k-means++ seeding of k rows of X (device float32 (n,d)) with the given
+    uniforms (k values in [0, 1)).  Returns ``(C, idx)`` (device tensors)."""
+    import numpy as np
+    torch = _torch()
+    n, d = X.shape
+    u = np.ascontiguousarray(uniforms, dtype=np.float64)
+    if u.shape != (k,):
+        raise ValueError("need %d uniforms" % k)
+    if C_out is None:
+        C_out = torch.empty((k, d), dtype=torch.float32, device=X.device)
+    if idx_out is None:
+        idx_out = torch.empty(k, dtype=torch.int32, device=X.device)
+    code = lib().kmeans_seed_pp(
+        ctx.handle, _dev_ptr(X, torch.float32, "X", n * d), n, d, int(k),
+        u.ctypes.data_as(ct.POINTER(ct.c_double)), _dev_ptr(C_out, torch.float32, "C_out", k * d),
+        _dev_ptr(idx_out, torch.int32, "idx_out", k, allow_none=True), _stream_ptr(stream),
+        KM_SYNC if sync else 0)
+    _check(code, "kmeans_seed_pp")
+    return C_out, idx_out
 
 
 def kmeans_lloyd_schedule(ctx: Context, X, C_inout, max_iter: int, early, late,

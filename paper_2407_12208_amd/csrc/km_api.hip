@@ -901,6 +901,32 @@ int32_t kmeans_lloyd(km_context* ctx, const float* X, int64_t n, int32_t d, int3
   return KM_OK;
 }
 
+int32_t kmeans_seed_pp(km_context* ctx, const float* X, int64_t n, int32_t d, int32_t k, const double* uniforms,
+                       float* C_out, int32_t* idx_out, void* stream, uint32_t flags) {
+  if (!ctx || !X || !uniforms || !C_out) return KM_ERR_ARG;
+  if (n < 1 || n > (int64_t)INT32_MAX - 1024 || d < 1 || d > 1024 || k < 1 || k > 65536 || k > n)
+    return KM_ERR_ARG;
+  for (int i = 0; i < k; ++i)
+    if (!(uniforms[i] >= 0.0 && uniforms[i] < 1.0)) return KM_ERR_ARG;
+  hipStream_t st = (hipStream_t)stream;
+  KM_HIP(hipSetDevice(ctx->device));
+  WorkspaceUse ws_use(ctx, st);
+  KM_HIP(ws_use.err);
+  const int64_t nblocks = (n + 1023) / 1024;
+  Plan pl;
+  pl.add<double>((size_t)n);
+  pl.add<double>((size_t)nblocks);
+  pl.add<int32_t>(1);
+  KM_HIP(ctx->arena.ensure(pl.bytes));
+  ctx->arena.reset();
+  double* w = ctx->arena.take<double>((size_t)n);
+  double* bsum = ctx->arena.take<double>((size_t)nblocks);
+  int32_t* pick = ctx->arena.take<int32_t>(1);
+  KM_HIP(launch_seed_pp(X, n, d, k, uniforms, C_out, idx_out, w, bsum, pick, st));
+  if (flags & KM_SYNC) KM_HIP(hipStreamSynchronize(st));
+  return KM_OK;
+}
+
 int32_t kmeans_lloyd_schedule(km_context* ctx, const float* X, int64_t n, int32_t d, int32_t k, float* C_inout,
                               int32_t max_iter, double tol, const km_precision* early, const km_precision* late,
                               double switch_rel, int32_t max_early, int32_t* labels, float* mindist,

@@ -177,6 +177,11 @@ inline OwnShape own_shape(int d, int k) {
   if (s.owners < 1) s = OwnShape{0, 0, 0};
   return s;
 }
+// k-means++ seeding (km_seed.hip); u: host array of k uniforms in [0, 1);
+// workspace w [n] FP64, bsum [ceil(n/1024)] FP64, pick [1] int32
+hipError_t launch_seed_pp(const float* X, int64_t n, int d, int k, const double* u, float* C, int32_t* idx,
+                          double* w, double* bsum, int32_t* pick, hipStream_t st);
+
 // LDS of one wave's accumulators and counts (16-byte multiple)
 inline int own_wave_bytes(int owners, int d, int k) {
   return (int)((((int64_t)owners * ((int64_t)k * d * 8 + (int64_t)k * 4)) + 15) / 16 * 16);

@@ -392,3 +392,31 @@ def test_schedule_equals_the_two_phases_and_obeys_its_rule(ctx, switch_rel, max_
     fmt_alpha = km.kmeans_alpha(FP16, 16)
     from tests.gpu_helpers import check_assignment
     check_assignment(X, host(C), 0, fmt_alpha, host(lab), host(md), h[-1], None)
+
+
+# ---------------------------------------------------------------------------
+# k-means++ seeding (D^2 weighting) against the oracle's O6
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("n,d,k", [(30_000, 16, 40), (100_003, 5, 64), (5_000, 128, 20), (1_500, 3, 1)])
+def test_seed_pp_matches_oracle(ctx, n, d, k):
+    X, _, _ = W.blobs(n, d, max(k, 2), seed=n + d)
+    u = np.random.default_rng(k).random(k)
+    C, idx = km.kmeans_seed_pp(ctx, dev(X), k, u)
+    ref = oracle.seed_pp(X, k, u)
+    # both sides sum FP64 weights in different orders; a different choice
+    # could only come from u * total landing within rounding of a boundary
+    np.testing.assert_array_equal(host(idx).astype(np.int64), ref)
+    np.testing.assert_array_equal(host(C), X[ref])
+
+
+def test_seed_pp_then_lloyd(ctx):
+    # seeding feeds Lloyd's algorithm: the final clustering of well separated
+    # blobs recovers the blobs (ARI 1 against the generating labels)
+    X, y, _ = W.blobs(20_000, 8, 12, seed=3, center_box=(-40, 40))
+    u = np.random.default_rng(4).random(12)
+    C, _ = km.kmeans_seed_pp(ctx, dev(X), 12, u)
+    _, lab, _, _, _ = km.kmeans_lloyd(ctx, dev(X), C, 30, prec=FP16)
+    assert km.kmeans_ari(host(lab), y) == pytest.approx(1.0)
+    assert km.kmeans_ami(host(lab), y) == pytest.approx(1.0)
+    assert km.kmeans_label_diff(host(lab), y) == 0.0

@@ -188,3 +188,40 @@ def test_uniform_fallback_loses_the_true_difference():
     # binary16 overflow of the running sum
     big = np.array([[200.0, 200.0]], dtype=np.float32)
     assert oracle.corr_rows(big, -big, 2, 0)[0, 0] == math.inf
+
+
+# ---------------------------------------------------------------------------
+# O6: k-means++ seeding by D^2 weighting
+# ---------------------------------------------------------------------------
+
+def test_seed_pp_worked_example_on_a_line():
+    # points 0, 1, 3, 10 on a line; first seed floor(0.3 * 4) = 1 (x = 1);
+    # weights to it: 1, 0, 4, 81 (total 86): u = 0.5 -> 43 falls in the last
+    # point's share; then weights 1, 0, 4, 0 (total 5): u = 0.3 -> 1.5 falls
+    # in point 2's share (1 < 1.5 <= 5)
+    X = np.array([[0.0], [1.0], [3.0], [10.0]], dtype=np.float32)
+    assert list(oracle.seed_pp(X, 3, [0.3, 0.5, 0.3])) == [1, 3, 2]
+    # u = 0 picks the first point of positive weight; a weight of zero is
+    # never picked, however u falls
+    assert list(oracle.seed_pp(X, 2, [0.3, 0.0])) == [1, 0]
+
+
+def test_seed_pp_draws_points_in_proportion_to_d2():
+    # with the first seed fixed, the second is point p with probability
+    # w_p / sum(w): the frequencies over a fine grid of u equal the shares
+    X = np.array([[0.0, 0.0], [1.0, 0.0], [0.0, 2.0], [3.0, 4.0], [-1.0, -1.0]], dtype=np.float32)
+    w = ((X - X[0]) ** 2).sum(1).astype(np.float64)
+    grid = (np.arange(20000) + 0.5) / 20000
+    counts = np.zeros(5)
+    for u in grid:
+        counts[oracle.seed_pp(X, 2, [0.0, u])[1]] += 1
+    np.testing.assert_allclose(counts / len(grid), w / w.sum(), atol=1e-4)
+
+
+def test_seed_pp_degenerate_and_distinct():
+    X = np.ones((6, 3), dtype=np.float32)  # all points coincide
+    assert list(oracle.seed_pp(X, 3, [0.0, 0.5, 0.99])) == [0, 3, 5]
+    g = np.random.default_rng(2)
+    Y = g.standard_normal((500, 4)).astype(np.float32)
+    idx = oracle.seed_pp(Y, 50, g.random(50))
+    assert len(set(idx.tolist())) == 50  # distinct points are never drawn twice
