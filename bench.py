@@ -505,20 +505,27 @@ def main():
         C0 = W.init_centroids(Xs, cs["k"], cs["init_seed"])
         Xs_d = torch.from_numpy(Xs).cuda()
         res = {}
-        for name, pr in (("mixed_fp16_fp64", prec), ("fp64_direct", p64)):
-            Cs = torch.from_numpy(C0).cuda()
-            km.kmeans_lloyd(ctx, Xs_d, Cs, cs["iters"], prec=pr, stats=False)
+        C0_d = torch.from_numpy(C0).cuda()
+        for name, pr, persistent in (("mixed_fp16_fp64", prec, False),
+                                     ("mixed_fp16_fp64_round_launch", prec, True),
+                                     ("fp64_direct", p64, False)):
+            Cs = C0_d.clone()
+            km.kmeans_lloyd(ctx, Xs_d, Cs, cs["iters"], prec=pr, stats=False,
+                            round_launch=persistent)
             torch.cuda.synchronize()
-            reps = 5
+            reps = 20
             ts = time.perf_counter()
             for _ in range(reps):
-                Cs.copy_(torch.from_numpy(C0).cuda())
-                km.kmeans_lloyd(ctx, Xs_d, Cs, cs["iters"], prec=pr, stats=False)
+                Cs.copy_(C0_d)
+                km.kmeans_lloyd(ctx, Xs_d, Cs, cs["iters"], prec=pr, stats=False,
+                                round_launch=persistent)
             torch.cuda.synchronize()
             dt = (time.perf_counter() - ts) / reps
             res[name] = cs["iters"] / dt
         extra["lloyd_small_iters_per_s"] = res["mixed_fp16_fp64"]
+        extra["lloyd_small_iters_per_s_round_launch"] = res["mixed_fp16_fp64_round_launch"]
         extra["lloyd_small_iters_per_s_fp64_direct"] = res["fp64_direct"]
+        extra["lloyd_small_speedup_vs_fp64_direct"] = res["mixed_fp16_fp64"] / res["fp64_direct"]
         if not args.no_large:
             extra["large_clustering"] = large_bench(km, ctx, torch, W, np)
         if args.batch_problems > 0:

@@ -136,6 +136,10 @@ typedef struct km_stats {
 #define KM_LABELS_HINT 2u /* kmeans_assign: labels holds an earlier assignment
                              (e.g. the previous Lloyd round); it only seeds
                              the search, the results are the same */
+#define KM_ROUND_LAUNCH 4u /* kmeans_lloyd: run all rounds in one persistent
+                              launch where the shape allows it (see
+                              kmeans_lloyd); the results are bitwise the
+                              same as with one launch per phase */
 
 typedef struct km_context km_context;
 typedef struct km_server km_server;
@@ -229,10 +233,19 @@ int32_t kmeans_update(km_context *ctx, const float *X, int64_t n, int32_t d,
  * C_inout holds the initial centres on entry and the final ones on exit.
  * Runs up to max_iter rounds of (assignment pass, centre update), stopping
  * after a round whose largest centre move is < tol (tol <= 0: never; a
- * positive tol costs one device-to-host read per round), then one final
- * assignment pass whose result fills labels / mindist.  sse_hist (device,
- * nullable, max_iter+1 entries) receives the SSE of each assignment pass in
- * order, the final one last.  max_iter = 0 performs the final pass only.
+ * positive tol costs one device-to-host read per round, or one per call when
+ * the rounds run in one launch), then one final assignment pass whose result
+ * fills labels / mindist.  sse_hist (device, nullable, max_iter+1 entries)
+ * receives the SSE of each assignment pass in order, the final one last.
+ * max_iter = 0 performs the final pass only.
+ * With KM_ROUND_LAUNCH in flags, small problems (FP16/BF16 operands,
+ * d <= 32, k <= 64) run all their rounds in one persistent launch: a grid of
+ * co-resident workgroups that assigns, updates and tests for convergence on
+ * the device, with grid-wide waits between the phases, so a positive tol
+ * costs no read per round and the host issues one launch per solve.  The
+ * results are bitwise those of one launch per phase (the default, which is
+ * the faster of the two when tol <= 0).  KM_ERR_DEVICE if such a wait ever
+ * gives up (it never should; the launch then ends instead of hanging).
  * Normalisation of the data (first line of the algorithm) is the caller's. */
 int32_t kmeans_lloyd(km_context *ctx, const float *X, int64_t n, int32_t d,
                      int32_t k, float *C_inout, int32_t max_iter, double tol,
@@ -358,8 +371,9 @@ int32_t kmeans_server_destroy(km_server *srv);
 
 /* ---- kernel timing (benchmarks) ----------------------------------------------
  * While enabled, every launch of the assignment kernel (the fused
- * mixed-precision kernel or the FP64 direct kernel) is bracketed by two HIP
- * events recorded on the launch's stream.  kmeans_timing_enable resets the
+ * mixed-precision kernel or the FP64 direct kernel) and every persistent
+ * round launch of kmeans_lloyd (all its rounds: one entry) is bracketed by
+ * two HIP events recorded on the launch's stream.  kmeans_timing_enable resets the
  * record.  kmeans_timing_read waits for the recorded events and copies up to
  * `max` durations (milliseconds, launch order) into ms_out; *count receives
  * the number recorded. */

@@ -32,6 +32,7 @@ KM_ALPHA_PAPER_EQ, KM_ALPHA_PAPER_ALG, KM_ALPHA_EXPLICIT, KM_ALPHA_NONE, KM_ALPH
 KM_HIGH_FP64, KM_HIGH_FP32, KM_HIGH_LOW = 0, 1, 2
 KM_SYNC = 1
 KM_LABELS_HINT = 2
+KM_ROUND_LAUNCH = 4
 KM_OK, KM_PENDING = 0, 1
 _STATUS_NAMES = {
     0: "KM_OK", 1: "KM_PENDING", -1: "KM_ERR_ARG", -2: "KM_ERR_RANGE",
@@ -369,8 +370,10 @@ def kmeans_update(ctx: Context, X, labels, C_old, C_new=None, counts=None,
 
 def kmeans_lloyd(ctx: Context, X, C_inout, max_iter: int, tol: float = 0.0,
                  prec=None, labels=None, mindist=None, sse_hist=None,
-                 stats=True, stream=None, sync=False):
+                 stats=True, stream=None, sync=False, round_launch=False):
     """Lloyd's algorithm; C_inout (k,d) float32 is updated in place.
+    ``round_launch`` sets KM_ROUND_LAUNCH (all rounds of a small problem in
+    one persistent launch).
     Returns ``(C_inout, labels, mindist, sse_hist, stats)``."""
     torch = _torch()
     n, d = X.shape
@@ -390,7 +393,7 @@ def kmeans_lloyd(ctx: Context, X, C_inout, max_iter: int, tol: float = 0.0,
         _dev_ptr(mindist, torch.float32, "mindist", n, allow_none=True),
         _dev_ptr(sse_hist, torch.float64, "sse_hist", max_iter + 1, allow_none=True),
         ct.byref(st) if st is not None else None, _stream_ptr(stream),
-        KM_SYNC if sync else 0)
+        (KM_SYNC if sync else 0) | (KM_ROUND_LAUNCH if round_launch else 0))
     _check(code, "kmeans_lloyd")
     return C_inout, labels, mindist, sse_hist, (st.as_dict() if st is not None else None)
 

@@ -114,6 +114,7 @@ int32_t status_from_bits(int bits) {
   if (bits & kStatusNonFinite) return KM_ERR_NONFINITE;
   if (bits & kStatusRange) return KM_ERR_RANGE;
   if (bits & kStatusBadLabel) return KM_ERR_ARG;  // label out of range in an update
+  if (bits & kStatusSync) return KM_ERR_DEVICE;   // persistent round kernel gave up a wait
   return KM_OK;
 }
 
@@ -313,7 +314,8 @@ hipError_t read_results(km_context_impl* ctx, const std::vector<const KResult*>&
 void plan_update(Plan& pl, int64_t n, int d, int k) {
   const OwnShape sh = own_shape(d, k);
   if (sh.owners > 0) {
-    const int64_t nch = (n + own_chunk(sh) - 1) / own_chunk(sh);
+    const int64_t cs = own_chunk(sh, own_iters(n, sh));
+    const int64_t nch = (n + cs - 1) / cs;
     pl.add<double>((size_t)nch * k * d);  // chunk partials
     pl.add<int32_t>((size_t)nch * k);     // chunk counts
     pl.add<double>((size_t)nch);          // chunk SSE partials
@@ -335,7 +337,10 @@ UpdateProb carve_update(Arena& a, int64_t n, int d, int k) {
   UpdateProb u{};
   const OwnShape sh = own_shape(d, k);
   if (sh.owners > 0) {
-    const int64_t nch = (n + own_chunk(sh) - 1) / own_chunk(sh);
+    const int iters = own_iters(n, sh);
+    const int64_t cs = own_chunk(sh, iters);
+    const int64_t nch = (n + cs - 1) / cs;
+    u.iters = iters;
     u.pacc = a.take<double>((size_t)nch * k * d);
     u.pcnt = a.take<int32_t>((size_t)nch * k);
     u.psse = a.take<double>((size_t)nch);
@@ -609,6 +614,49 @@ PassBufs carve_pass(Arena& ar, const AssignPlan& a) {
 
 bool uses_prep(const AssignPlan& a) { return a.route == Route::Mfma || a.route == Route::MfmaNoFallback; }
 
+// Descriptor of one assignment pass of one problem.
+static AssignProb pass_assign_prob(const AssignPlan& a, const PassBufs& b, const float* X, int64_t n, int d,
+                                   const float* C, int k, int32_t* labels, float* mindist, float* D,
+                                   uint8_t* flagged, bool refine, bool hint) {
+  AssignProb ap{};
+  ap.X = X;
+  ap.C = C;
+  ap.Cq = b.Cq;
+  ap.cinit = b.cinit;
+  ap.ca = b.ca;
+  ap.labels = labels;
+  ap.mindist = mindist;
+  ap.D = D;
+  ap.flagged = flagged;
+  ap.sse_part = b.sse_part;
+  ap.corr_part = b.corr_part;
+  ap.status = b.status;
+  ap.n = n;
+  ap.d = d;
+  ap.k = k;
+  ap.k_pad = a.k_pad;
+  ap.oma = a.oma;
+  ap.refine = refine ? 1 : 0;
+  ap.hint = hint ? labels : nullptr;
+  ap.gpw = a.gpw;
+  ap.alpha = a.alpha_f;
+  ap.high = a.high;
+  return ap;
+}
+
+// Reduction of a pass's per-workgroup partials into the result record.
+static ReduceProb pass_reduce_prob(const PassBufs& b, int64_t n, int k, double* sse_slot, int nparts) {
+  ReduceProb rp{};
+  rp.sse_part = b.sse_part;
+  rp.corr_part = b.corr_part;
+  rp.status = b.status;
+  rp.sse_out = sse_slot;
+  rp.result = b.result;
+  rp.pairs = n * (long long)k;
+  rp.nparts = nparts;
+  return rp;
+}
+
 // Enqueue one assignment pass (prep + assign + reduce) of one problem.
 static hipError_t enqueue_pass(km_context_impl* ctx, const AssignPlan& a, const PassBufs& b,
                                const float* X, int64_t n, int d, const float* C, int k, int32_t* labels,
@@ -637,41 +685,12 @@ static hipError_t enqueue_pass(km_context_impl* ctx, const AssignPlan& a, const 
     o_pp = pk.add(&pp, sizeof(pp));
     o_ps = pk.add(pre, sizeof(pre));
   }
-  AssignProb ap{};
-  ap.X = X;
-  ap.C = C;
-  ap.Cq = b.Cq;
-  ap.cinit = b.cinit;
-  ap.ca = b.ca;
-  ap.labels = labels;
-  ap.mindist = mindist;
-  ap.D = D;
-  ap.flagged = flagged;
-  ap.sse_part = b.sse_part;
-  ap.corr_part = b.corr_part;
-  ap.status = b.status;
-  ap.n = n;
-  ap.d = d;
-  ap.k = k;
-  ap.k_pad = a.k_pad;
-  ap.oma = a.oma;
-  ap.refine = refine ? 1 : 0;
-  ap.hint = hint ? labels : nullptr;
-  ap.gpw = a.gpw;
-  ap.alpha = a.alpha_f;
-  ap.high = a.high;
+  const AssignProb ap = pass_assign_prob(a, b, X, n, d, C, k, labels, mindist, D, flagged, refine, hint);
   const int nwg = mode == 0 ? a.nwg : a.nwg_pair;
   const int32_t apre[2] = {0, nwg};
   const size_t o_ap = pk.add(&ap, sizeof(ap));
   const size_t o_as = pk.add(apre, sizeof(apre));
-  ReduceProb rp{};
-  rp.sse_part = b.sse_part;
-  rp.corr_part = b.corr_part;
-  rp.status = b.status;
-  rp.sse_out = sse_slot;
-  rp.result = b.result;
-  rp.pairs = n * (long long)k;
-  rp.nparts = nwg;
+  const ReduceProb rp = pass_reduce_prob(b, n, k, sse_slot, nwg);
   const size_t o_rp = pk.add(&rp, sizeof(rp));
   char* dv = pk.upload(ctx, st);
   if (!dv) return hipErrorOutOfMemory;
@@ -843,6 +862,85 @@ int32_t kmeans_update(km_context* ctx, const float* X, int64_t n, int32_t d, con
   return KM_OK;
 }
 
+}  // extern "C"
+
+namespace km {
+
+// Lloyd rounds that one persistent launch can run: the small-problem
+// assignment kernel and the owner path of the update.
+static bool rounds_fit(const AssignPlan& a, const UpdateProb& u) {
+  return a.xd > 0 && (a.route == Route::Mfma || a.route == Route::MfmaNoFallback) && u.owners > 0 && u.nc == 1;
+}
+
+// Enqueues every round of one problem in one persistent launch (C0 holds the
+// initial centres, rounds alternate C0 -> C1 -> C0 ...).  *ran = false when
+// the runtime refuses the co-resident grid: nothing ran and the caller runs
+// its launch-per-phase loop.
+static hipError_t enqueue_rounds(km_context_impl* ctx, const AssignPlan& a, const PassBufs& b,
+                                 const UpdateProb& u0, const float* X, int64_t n, int d, int k, float* C0,
+                                 float* C1, int32_t* labels, double* sse_hist, int max_iter, double tol, int* ctl,
+                                 bool* ran, hipStream_t st) {
+  *ran = false;
+  RoundProb R{};
+  for (int q = 0; q < 2; ++q) {
+    float* c_old = q == 0 ? C0 : C1;
+    float* c_new = q == 0 ? C1 : C0;
+    R.a[q] = pass_assign_prob(a, b, X, n, d, c_old, k, labels, nullptr, nullptr, nullptr, false, false);
+    R.u[q] = u0;
+    R.u[q].C_old = c_old;
+    R.u[q].C_new = c_new;
+    R.u[q].sse_out = nullptr;
+  }
+  R.red = pass_reduce_prob(b, n, k, nullptr, a.nwg);
+  R.sse_hist = sse_hist;
+  R.tol = tol;
+  R.max_iter = max_iter;
+  const int J = own_fin_clusters(d);
+  R.nfin = (k + J - 1) / J;
+  R.wstride = std::max(16, own_wave_bytes(u0.owners, d, k));
+  const int32_t tpre[2] = {0, a.nwg};
+  const int32_t cpre[2] = {0, u0.nchunk};
+  const int32_t fpre[2] = {0, 1 + R.nfin};
+  Pack pk;
+  const size_t o_r = pk.add(&R, sizeof(R));
+  const size_t o_t = pk.add(tpre, sizeof(tpre));
+  const size_t o_c = pk.add(cpre, sizeof(cpre));
+  const size_t o_f = pk.add(fpre, sizeof(fpre));
+  char* dv = pk.upload(ctx, st);
+  if (!dv) return hipErrorOutOfMemory;
+  hipError_t e = launch_zero_words(ctl, sizeof(int) * (size_t)round_ctl_words(1), st);
+  if (e != hipSuccess) return e;
+  const bool fb = a.route == Route::Mfma;
+  const int lds = std::max(small_lds_bytes(a.xd, fb), kOwnWaves * R.wstride + 4 * k * d);
+  // with timing on, the whole launch is one entry of the record
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (ctx->timing) {
+    e0 = ctx->timing_event(2 * ctx->ev_used);
+    e1 = ctx->timing_event(2 * ctx->ev_used + 1);
+    if (!e0 || !e1) return hipErrorOutOfMemory;
+    e = hipEventRecord(e0, st);
+    if (e != hipSuccess) return e;
+  }
+  e = launch_lloyd_rounds(a.low, a.xd, fb, (const RoundProb*)(dv + o_r), 1, (const int32_t*)(dv + o_t),
+                          (const int32_t*)(dv + o_c), (const int32_t*)(dv + o_f), ctl,
+                          std::max(a.nwg, u0.nchunk), lds, st);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return hipSuccess;
+  }
+  *ran = true;
+  if (ctx->timing) {
+    e = hipEventRecord(e1, st);
+    if (e != hipSuccess) return e;
+    ctx->ev_used += 1;
+  }
+  return hipSuccess;
+}
+
+}  // namespace km
+
+extern "C" {
+
 int32_t kmeans_lloyd(km_context* ctx, const float* X, int64_t n, int32_t d, int32_t k, float* C_inout,
                      int32_t max_iter, double tol, const km_precision* prec, int32_t* labels, float* mindist,
                      double* sse_hist, km_stats* stats, void* stream, uint32_t flags) {
@@ -861,11 +959,13 @@ int32_t kmeans_lloyd(km_context* ctx, const float* X, int64_t n, int32_t d, int3
   plan_pass(pl, a);
   plan_update(pl, n, d, k);
   pl.add<float>((size_t)k * d);  // second centre buffer
+  pl.add<int>((size_t)round_ctl_words(1));
   KM_HIP(ctx->arena.ensure(pl.bytes));
   ctx->arena.reset();
   PassBufs b = carve_pass(ctx->arena, a);
   UpdateProb u = carve_update(ctx->arena, n, d, k);
   float* Cw = ctx->arena.take<float>((size_t)k * d);
+  int* ctl = ctx->arena.take<int>((size_t)round_ctl_words(1));
   KM_HIP(zero_status_result(b.status, b.result, st));
   u.X = X;
   u.labels = labels;
@@ -874,7 +974,22 @@ int32_t kmeans_lloyd(km_context* ctx, const float* X, int64_t n, int32_t d, int3
   float* cur = C_inout;
   float* nxt = Cw;
   int32_t it = 0;
-  for (; it < max_iter; ++it) {
+  bool ran = false;
+  if (max_iter > 0 && (flags & KM_ROUND_LAUNCH) && rounds_fit(a, u)) {
+    KM_HIP(enqueue_rounds(ctx, a, b, u, X, n, d, k, C_inout, Cw, labels, sse_hist, max_iter, tol, ctl, &ran, st));
+    if (ran) {
+      it = max_iter;
+      if (tol > 0.0) {  // the rounds run are known on the device only
+        int* h = reinterpret_cast<int*>(ctx->h_result);
+        KM_HIP(hipMemcpyAsync(h, ctl, sizeof(int) * (size_t)round_ctl_words(1), hipMemcpyDeviceToHost, st));
+        KM_HIP(hipStreamSynchronize(st));
+        if (h[1] != 0) return KM_ERR_DEVICE;
+        it = h[3];
+      }
+      if (it & 1) std::swap(cur, nxt);
+    }
+  }
+  for (; !ran && it < max_iter; ++it) {
     // the SSE of a round's pass comes from the update, which reads every
     // point's row against the centre it was assigned to
     KM_HIP(enqueue_pass(ctx, a, b, X, n, d, cur, k, labels, nullptr, nullptr, 0, nullptr, nullptr, false,

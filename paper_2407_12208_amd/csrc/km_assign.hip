@@ -22,6 +22,7 @@
 // problem's arithmetic never depends on the other problems in the launch.
 #include "km_device.hpp"
 #include "km_internal.hpp"
+#include "km_update_dev.hpp"
 
 namespace km {
 
@@ -1174,32 +1175,37 @@ __device__ inline double sqdist64_rl(const float (&x)[XD], const float* c, int d
   return s;
 }
 
+// LDS of one workgroup of the small-problem body: FP32 centre rows, their
+// accumulator starts and test constants, and per wave the correction queue of
+// a 32-centre block (at most 32 x 32 pairs), the group's point rows and each
+// point's best corrected pair.
+template <int XD, bool FALLBACK>
+struct SmallLds {
+  static constexpr int CS = XD + 4;  // LDS row stride of FP32 rows (16-byte aligned)
+  alignas(16) float ca[kSmallMaxK];
+  alignas(16) float cinit[kSmallMaxK];
+  alignas(16) float c[kSmallMaxK * CS];
+  alignas(16) float x[FALLBACK ? kSmallWaves : 1][FALLBACK ? 32 * CS : 4];
+  unsigned long long key[FALLBACK ? kSmallWaves : 1][32];
+  double sse[kSmallWaves];
+  unsigned long long corr[kSmallWaves];
+  int q[FALLBACK ? kSmallWaves : 1][FALLBACK ? 32 * 32 : 1];
+};
+
+// One tile (kSmallWaves x 32 x gpw consecutive points) of a problem; writes
+// the tile's labels and its SSE / corrected-pair partials.
 template <class L, int XD, bool FALLBACK>
-__global__ void __launch_bounds__(kSmallThreads, XD == 8 ? 4 : XD == 16 ? 3 : 2)
-k_assign_small(const AssignProb* __restrict__ probs, const int32_t* __restrict__ wg_start, int nprob) {
+__device__ __attribute__((always_inline)) inline void
+assign_small_tile(const AssignProb& P, const int tile, SmallLds<XD, FALLBACK>& sm) {
   constexpr int DP = XD < 16 ? 16 : XD;  // row extent of the quantised centres
   constexpr int STEPS = DP / L::KS;
-  constexpr int CS = XD + 4;             // LDS row stride of FP32 rows (16-byte aligned)
+  constexpr int CS = XD + 4;
   using S = typename L::S;
   using frag = typename L::frag;
-  __shared__ __attribute__((aligned(16))) float s_ca[kSmallMaxK];
-  __shared__ __attribute__((aligned(16))) float s_cinit[kSmallMaxK];
-  __shared__ __attribute__((aligned(16))) float s_c[kSmallMaxK * CS];
-  // correction queue of a 32-centre block (at most 32 x 32 pairs), the
-  // group's point rows and each point's best corrected pair
-  __shared__ int s_q[FALLBACK ? kSmallWaves : 1][FALLBACK ? 32 * 32 : 1];
-  __shared__ __attribute__((aligned(16))) float s_x[FALLBACK ? kSmallWaves : 1][FALLBACK ? 32 * CS : 4];
-  __shared__ unsigned long long s_key[FALLBACK ? kSmallWaves : 1][32];
-  __shared__ double s_sse[kSmallWaves];
-  __shared__ unsigned long long s_corr[kSmallWaves];
-
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = tid >> 6;
   const int hi = lane >> 5;
-  const int pi = find_problem(wg_start, nprob, blockIdx.x);
-  const AssignProb& P = probs[pi];
-  const int tile = blockIdx.x - wg_start[pi];
   const int gpw = P.gpw;
   const int64_t p0 = (int64_t)tile * (kSmallWaves * 32) * gpw;
   const int64_t n = P.n;
@@ -1244,7 +1250,7 @@ k_assign_small(const AssignProb* __restrict__ probs, const int32_t* __restrict__
       if (!__builtin_isfinite(v)) bad |= kStatusNonFinite;
       if (L::kHasRange && __builtin_fabsf(v) >= L::kOverflow) bad |= kStatusRange;
     }
-    s_c[e] = v;
+    sm.c[e] = v;
   }
   __syncthreads();
   if (tid < kSmallMaxK) {
@@ -1252,12 +1258,12 @@ k_assign_small(const AssignProb* __restrict__ probs, const int32_t* __restrict__
 #pragma unroll
     for (int l = 0; l < XD; ++l) {
       if (l >= d) break;
-      const float f = L::tof(L::cvt(s_c[tid * CS + l]));
+      const float f = L::tof(L::cvt(sm.c[tid * CS + l]));
       nc = __builtin_fmaf(f, f, nc);
     }
     const float hc = 0.5f * nc;
-    s_cinit[tid] = tid < k ? -hc : -__builtin_inff();
-    s_ca[tid] = tid < k ? P.alpha * hc : 0.0f;
+    sm.cinit[tid] = tid < k ? -hc : -__builtin_inff();
+    sm.ca[tid] = tid < k ? P.alpha * hc : 0.0f;
   }
   // centre fragments in registers: RNE of the LDS rows (zero past d and k)
   frag af[2][STEPS];
@@ -1268,7 +1274,7 @@ k_assign_small(const AssignProb* __restrict__ probs, const int32_t* __restrict__
 #pragma unroll
       for (int u = 0; u < L::KV; ++u) {
         const int l = s * L::KS + hi * L::KV + u;
-        const float v = (b < kb && l < XD) ? s_c[(b * 32 + (lane & 31)) * CS + (l < XD ? l : 0)] : 0.0f;
+        const float v = (b < kb && l < XD) ? sm.c[(b * 32 + (lane & 31)) * CS + (l < XD ? l : 0)] : 0.0f;
         af[b][s][u] = L::cvt(v);
       }
     }
@@ -1278,7 +1284,7 @@ k_assign_small(const AssignProb* __restrict__ probs, const int32_t* __restrict__
     f32x16 a;
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-      const f32x4 v = *reinterpret_cast<const f32x4*>(&s_cinit[b * 32 + 8 * q + 4 * hi]);
+      const f32x4 v = *reinterpret_cast<const f32x4*>(&sm.cinit[b * 32 + 8 * q + 4 * hi]);
       a[4 * q] = v[0]; a[4 * q + 1] = v[1]; a[4 * q + 2] = v[2]; a[4 * q + 3] = v[3];
     }
     return a;
@@ -1298,7 +1304,7 @@ k_assign_small(const AssignProb* __restrict__ probs, const int32_t* __restrict__
   for (int b = 0; b < 2; ++b) {
     float m = -__builtin_inff();
 #pragma unroll
-    for (int r = 0; r < 16; ++r) m = __builtin_fmaxf(m, s_ca[b * 32 + acc_row(r, lane)]);
+    for (int r = 0; r < 16; ++r) m = __builtin_fmaxf(m, sm.ca[b * 32 + acc_row(r, lane)]);
     cam[b] = m;
   }
 
@@ -1363,7 +1369,7 @@ k_assign_small(const AssignProb* __restrict__ probs, const int32_t* __restrict__
           uint32_t fm = 0;
 #pragma unroll
           for (int q = 0; q < 4; ++q) {  // rows 8q + 4hi + 0..3 of the block
-            const f32x4 ca4 = *reinterpret_cast<const f32x4*>(&s_ca[b * 32 + 8 * q + 4 * hi]);
+            const f32x4 ca4 = *reinterpret_cast<const f32x4*>(&sm.ca[b * 32 + 8 * q + 4 * hi]);
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
               const int r = 4 * q + e;
@@ -1379,9 +1385,9 @@ k_assign_small(const AssignProb* __restrict__ probs, const int32_t* __restrict__
             if (hi == 0) {  // whole rows: the coordinates past d are zero
 #pragma unroll
               for (int l = 0; l < XD; l += 4)
-                *reinterpret_cast<f32x4*>(&s_x[wave][(lane & 31) * CS + l]) =
+                *reinterpret_cast<f32x4*>(&sm.x[wave][(lane & 31) * CS + l]) =
                     f32x4{x[l], x[l + 1], x[l + 2], x[l + 3]};
-              s_key[wave][lane & 31] = ~0ull;
+              sm.key[wave][lane & 31] = ~0ull;
             }
           }
           // queue positions: exclusive prefix of the lanes' flag counts
@@ -1399,14 +1405,14 @@ k_assign_small(const AssignProb* __restrict__ probs, const int32_t* __restrict__
           while (fm) {
             const int r = __builtin_ctz(fm);
             fm &= fm - 1;
-            s_q[wave][pos++] = (lane & 31) | ((b * 32 + acc_row(r, lane)) << 5);
+            sm.q[wave][pos++] = (lane & 31) | ((b * 32 + acc_row(r, lane)) << 5);
           }
           wave_lds_sync();
           for (int e = lane; e < total; e += 64) {
-            const int code = s_q[wave][e];
+            const int code = sm.q[wave][e];
             const int pt = code & 31, j = code >> 5;
-            const float* xr = &s_x[wave][pt * CS];
-            const float* cr = &s_c[j * CS];
+            const float* xr = &sm.x[wave][pt * CS];
+            const float* cr = &sm.c[j * CS];
             // four coordinates per LDS access; both rows are zero past d,
             // and a zero term leaves the FP64 sum unchanged
             double sq = 0.0;
@@ -1429,7 +1435,7 @@ k_assign_small(const AssignProb* __restrict__ probs, const int32_t* __restrict__
             // non-negative value order like the value
             const unsigned long long key =
                 ((unsigned long long)__float_as_uint((float)sq) << 32) | (unsigned)j;
-            atomicMin(&s_key[wave][pt], key);
+            atomicMin(&sm.key[wave][pt], key);
             ncorr += 1;
           }
           wave_lds_sync();
@@ -1439,7 +1445,7 @@ k_assign_small(const AssignProb* __restrict__ probs, const int32_t* __restrict__
     float cd = __builtin_inff();
     int cj = -1;
     if (staged) {
-      const unsigned long long key = s_key[wave][lane & 31];
+      const unsigned long long key = sm.key[wave][lane & 31];
       if (key != ~0ull) {
         cj = (int)(key & 0xffffffffu);
         cd = __uint_as_float((unsigned)(key >> 32));
@@ -1470,7 +1476,7 @@ k_assign_small(const AssignProb* __restrict__ probs, const int32_t* __restrict__
       if (lab < 0 || lab >= k) lab = 0;  // only with non-finite data (status raised)
       as_global(P.labels)[p] = lab;
       if (P.refine) {
-        const double dd = sqdist64_rl<XD>(x, s_c + lab * CS, d);
+        const double dd = sqdist64_rl<XD>(x, sm.c + lab * CS, d);
         if (P.mindist) as_global(P.mindist)[p] = (float)dd;
         sse += dd;
       }
@@ -1480,8 +1486,8 @@ k_assign_small(const AssignProb* __restrict__ probs, const int32_t* __restrict__
   sse = wave_sum(sse);
   const unsigned long long nc = wave_sum_u64(ncorr);
   if (lane == 0) {
-    s_sse[wave] = sse;
-    s_corr[wave] = nc;
+    sm.sse[wave] = sse;
+    sm.corr[wave] = nc;
   }
   __syncthreads();
   if (tid == 0) {
@@ -1489,12 +1495,169 @@ k_assign_small(const AssignProb* __restrict__ probs, const int32_t* __restrict__
     unsigned long long c = 0;
 #pragma unroll
     for (int w = 0; w < kSmallWaves; ++w) {
-      ssum += s_sse[w];
-      c += s_corr[w];
+      ssum += sm.sse[w];
+      c += sm.corr[w];
     }
     as_global(P.sse_part)[tile] = ssum;
     as_global(P.corr_part)[tile] = c;
   }
+}
+
+template <class L, int XD, bool FALLBACK>
+__global__ void __launch_bounds__(kSmallThreads, XD == 8 ? 4 : XD == 16 ? 3 : 2)
+k_assign_small(const AssignProb* __restrict__ probs, const int32_t* __restrict__ wg_start, int nprob) {
+  __shared__ SmallLds<XD, FALLBACK> sm;
+  const int pi = find_problem(wg_start, nprob, blockIdx.x);
+  assign_small_tile<L, XD, FALLBACK>(probs[pi], blockIdx.x - wg_start[pi], sm);
+}
+
+// ---------------------------------------------------------------------------
+// Persistent Lloyd rounds of small problems (descriptor in km_internal.hpp).
+// The grid is co-resident (cooperative launch); the phases of a round are
+// separated by grid-wide waits on an arrival counter: release of the
+// workgroup's writes at agent scope, one relaxed increment, then polling until
+// every workgroup of the grid has arrived, and an agent-scope acquire.  The
+// counter only grows (target = waits so far x grid size), so no reset is
+// needed.  A wait that polls for more than kSyncSpins rounds (far beyond any
+// phase) raises the abort flag; every other waiting workgroup sees it and
+// leaves, so the kernel always ends, and every problem's status gets
+// kStatusSync.
+// ---------------------------------------------------------------------------
+// Fixed-order sums of a pass's per-workgroup partials into its result record
+// (ss, sc: 256 entries of LDS each)
+__device__ __attribute__((always_inline)) inline void
+reduce_parts_prob(const ReduceProb& P, double* ss, unsigned long long* sc) {
+  const int tid = threadIdx.x;
+  double s = 0.0;
+  unsigned long long c = 0;
+  for (int i = tid; i < P.nparts; i += 256) {
+    s += as_global(P.sse_part)[i];
+    c += as_global(P.corr_part)[i];
+  }
+  ss[tid] = s;
+  sc[tid] = c;
+  __syncthreads();
+  for (int o = 128; o >= 1; o >>= 1) {
+    if (tid < o) {
+      ss[tid] += ss[tid + o];
+      sc[tid] += sc[tid + o];
+    }
+    __syncthreads();
+  }
+  if (tid == 0) {
+    if (P.sse_out) *P.sse_out = ss[0];
+    if (P.result) {
+      P.result->sse = ss[0];
+      P.result->n_corrected += (long long)sc[0];
+      P.result->n_pairs += P.pairs;
+      P.result->status |= *P.status;
+    }
+  }
+}
+
+constexpr unsigned kSyncSpins = 1u << 25;  // s_sleep(2) polls: well over a second
+
+__device__ inline bool grid_wait(int* ctl, unsigned target, int* s_ok) {
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    unsigned* arrivals = reinterpret_cast<unsigned*>(ctl);
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    __hip_atomic_fetch_add(arrivals, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    int ok = 1;
+    unsigned spins = 0;
+    while (__hip_atomic_load(arrivals, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+      if (__hip_atomic_load(ctl + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0 || ++spins > kSyncSpins) {
+        ok = 0;
+        break;
+      }
+      __builtin_amdgcn_s_sleep(2);
+    }
+    if (!ok) __hip_atomic_fetch_or(ctl + 1, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    *s_ok = ok;
+  }
+  __syncthreads();
+  return *s_ok != 0;
+}
+
+__device__ inline int load_agent(const int* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Dynamic LDS: max(SmallLds, the update's wave regions and C_old), shared by
+// the phases (a grid-wide wait separates them).
+// (two workgroups per compute unit at most: the update's LDS rarely allows
+// more, and the fused body then keeps its registers)
+template <class L, int XD, bool FALLBACK>
+__global__ void __launch_bounds__(kSmallThreads, 2)
+k_lloyd_rounds(const RoundProb* __restrict__ probs, int nprob, const int32_t* __restrict__ tpre,
+               const int32_t* __restrict__ cpre, const int32_t* __restrict__ fpre, int* ctl) {
+  extern __shared__ __attribute__((aligned(16))) char s_dyn[];
+  __shared__ double s_sse[kOwnWaves];
+  __shared__ double s_red[256];
+  __shared__ unsigned long long s_cnt[256];
+  __shared__ int s_m[256];
+  __shared__ int s_ok;
+  __shared__ unsigned char s_done[kRoundMaxProbs];  // this round's done flags
+  SmallLds<XD, FALLBACK>& sm = *reinterpret_cast<SmallLds<XD, FALLBACK>*>(s_dyn);
+  int* done = ctl + 2;
+  int* rounds = ctl + 2 + nprob;
+  const int G = gridDim.x;
+  const int ntile = tpre[nprob], nchunk = cpre[nprob], nfin = fpre[nprob];
+  unsigned waits = 0;
+  for (int r = 0;; ++r) {
+    const int b = r & 1;
+    // done flags (written by the previous round's last phase) once per round
+    int live = 0;
+    for (int i = threadIdx.x; i < nprob; i += kSmallThreads) {
+      const int dn = load_agent(done + i);
+      s_done[i] = (unsigned char)dn;
+      live |= dn == 0;
+    }
+    if (!__syncthreads_or(live)) return;
+    // assignment of every tile of the running problems
+    for (int t = blockIdx.x; t < ntile; t += G) {
+      const int pi = find_problem(tpre, nprob, t);
+      if (s_done[pi]) continue;
+      assign_small_tile<L, XD, FALLBACK>(probs[pi].a[b], t - tpre[pi], sm);
+      __syncthreads();
+    }
+    if (!grid_wait(ctl, ++waits * (unsigned)G, &s_ok)) break;
+    // chunk partials of the centre update
+    for (int c = blockIdx.x; c < nchunk; c += G) {
+      const int pi = find_problem(cpre, nprob, c);
+      if (s_done[pi]) continue;
+      own_part_chunk<1, true>(probs[pi].u[b], c - cpre[pi], s_dyn, probs[pi].wstride, s_sse);
+      __syncthreads();
+    }
+    if (!grid_wait(ctl, ++waits * (unsigned)G, &s_ok)) break;
+    // per problem: counters of the pass (item 0), new centres of each
+    // cluster group (items 1..nfin)
+    for (int f = blockIdx.x; f < nfin; f += G) {
+      const int pi = find_problem(fpre, nprob, f);
+      if (s_done[pi]) continue;
+      const int item = f - fpre[pi];
+      if (item == 0) reduce_parts_prob(probs[pi].red, s_red, s_cnt);
+      else own_fin_group(probs[pi].u[b], item - 1, s_m, s_red);
+      __syncthreads();
+    }
+    if (!grid_wait(ctl, ++waits * (unsigned)G, &s_ok)) break;
+    // per problem: shift, SSE, stop test
+    for (int pi = blockIdx.x; pi < nprob; pi += G) {
+      if (s_done[pi]) continue;
+      const RoundProb& R = probs[pi];
+      const double shift = own_shift_prob(R.u[b], R.sse_hist ? R.sse_hist + r : nullptr, s_red);
+      if (threadIdx.x == 0) {
+        rounds[pi] = r + 1;
+        if (r + 1 >= R.max_iter || (R.tol > 0.0 && shift < R.tol)) done[pi] = 1;
+      }
+      __syncthreads();
+    }
+    if (!grid_wait(ctl, ++waits * (unsigned)G, &s_ok)) break;
+  }
+  // a wait gave up: mark every problem (the result records carry it)
+  if (blockIdx.x == 0 && threadIdx.x == 0)
+    for (int i = 0; i < nprob; ++i) atomicOr(probs[i].a[0].status, kStatusSync);
 }
 
 // ---------------------------------------------------------------------------
@@ -1732,37 +1895,12 @@ k_assign_direct64(const AssignProb* __restrict__ probs, const int32_t* __restric
 // problem.  Writes the SSE to the caller's scalar (if any) and the problem's
 // result record (SSE, corrected pairs, status).
 // ---------------------------------------------------------------------------
+
 __global__ void __launch_bounds__(256)
 k_reduce_parts(const ReduceProb* __restrict__ probs) {
-  const ReduceProb& P = probs[blockIdx.x];
   __shared__ double ss[256];
   __shared__ unsigned long long sc[256];
-  const int tid = threadIdx.x;
-  double s = 0.0;
-  unsigned long long c = 0;
-  for (int i = tid; i < P.nparts; i += 256) {
-    s += as_global(P.sse_part)[i];
-    c += as_global(P.corr_part)[i];
-  }
-  ss[tid] = s;
-  sc[tid] = c;
-  __syncthreads();
-  for (int o = 128; o >= 1; o >>= 1) {
-    if (tid < o) {
-      ss[tid] += ss[tid + o];
-      sc[tid] += sc[tid + o];
-    }
-    __syncthreads();
-  }
-  if (tid == 0) {
-    if (P.sse_out) *P.sse_out = ss[0];
-    if (P.result) {
-      P.result->sse = ss[0];
-      P.result->n_corrected += (long long)sc[0];
-      P.result->n_pairs += P.pairs;
-      P.result->status |= *P.status;
-    }
-  }
+  reduce_parts_prob(probs[blockIdx.x], ss, sc);
 }
 
 template <class L>
@@ -1871,6 +2009,50 @@ hipError_t launch_assign_small(int low, int xd, bool fallback, const AssignProb*
     return fallback ? launch_small_t<LowBF16, true>(xd, dprobs, dstart, nprob, nwg, st)
                     : launch_small_t<LowBF16, false>(xd, dprobs, dstart, nprob, nwg, st);
   return hipErrorInvalidValue;
+}
+
+template <class L, bool FALLBACK>
+static hipError_t launch_rounds_t(int xd, const RoundProb* dprobs, int nprob, const int32_t* tpre,
+                                  const int32_t* cpre, const int32_t* fpre, int* ctl, int work_items,
+                                  int lds_bytes, hipStream_t st) {
+  const void* f = nullptr;
+  switch (xd) {
+    case 8: f = reinterpret_cast<const void*>(&k_lloyd_rounds<L, 8, FALLBACK>); break;
+    case 16: f = reinterpret_cast<const void*>(&k_lloyd_rounds<L, 16, FALLBACK>); break;
+    case 32: f = reinterpret_cast<const void*>(&k_lloyd_rounds<L, 32, FALLBACK>); break;
+    default: return hipErrorInvalidValue;
+  }
+  hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, lds_bytes);
+  if (e != hipSuccess) return e;
+  int dev = 0, cus = 0, per_cu = 0;
+  e = hipGetDevice(&dev);
+  if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, f, kSmallThreads, lds_bytes);
+  if (e != hipSuccess) return e;
+  if (per_cu < 1 || cus < 1) return hipErrorInvalidConfiguration;
+  const int grid = std::max(1, std::min(per_cu * cus, work_items));
+  void* args[] = {(void*)&dprobs, (void*)&nprob, (void*)&tpre, (void*)&cpre, (void*)&fpre, (void*)&ctl};
+  return hipLaunchCooperativeKernel(f, dim3(grid), dim3(kSmallThreads), args, (unsigned)lds_bytes, st);
+}
+
+hipError_t launch_lloyd_rounds(int low, int xd, bool fallback, const RoundProb* dprobs, int nprob,
+                               const int32_t* tpre, const int32_t* cpre, const int32_t* fpre, int* ctl,
+                               int work_items, int lds_bytes, hipStream_t st) {
+#define KM_ROUNDS(L, F) launch_rounds_t<L, F>(xd, dprobs, nprob, tpre, cpre, fpre, ctl, work_items, lds_bytes, st)
+  if (low == kLowFP16) return fallback ? KM_ROUNDS(LowF16, true) : KM_ROUNDS(LowF16, false);
+  if (low == kLowBF16) return fallback ? KM_ROUNDS(LowBF16, true) : KM_ROUNDS(LowBF16, false);
+#undef KM_ROUNDS
+  return hipErrorInvalidValue;
+}
+
+// LDS of the persistent round kernel's assignment body
+int small_lds_bytes(int xd, bool fallback) {
+  switch (xd) {
+    case 8: return fallback ? (int)sizeof(SmallLds<8, true>) : (int)sizeof(SmallLds<8, false>);
+    case 16: return fallback ? (int)sizeof(SmallLds<16, true>) : (int)sizeof(SmallLds<16, false>);
+    case 32: return fallback ? (int)sizeof(SmallLds<32, true>) : (int)sizeof(SmallLds<32, false>);
+  }
+  return 0;
 }
 
 hipError_t launch_assign_direct64(bool cmp64, int arith, int mode, const AssignProb* dprobs,

@@ -17,6 +17,7 @@ constexpr int kExact64 = 3;
 constexpr int kStatusNonFinite = 1;
 constexpr int kStatusRange = 2;
 constexpr int kStatusBadLabel = 4;
+constexpr int kStatusSync = 8;  // a grid-wide wait of the persistent round kernel gave up
 
 // Padded coordinate extent of the matrix-core kernels (multiple of the K
 // extent of one instruction; 16 for every format so layouts agree).
@@ -128,6 +129,7 @@ struct UpdateProb {
   int32_t* pcnt;           // nchunk * k
   double* psse;            // nchunk
   int owners, lp, nc, nchunk;
+  int iters;               // points per owner per chunk (own_iters)
 };
 
 hipError_t launch_prep(int low, const PrepProb* dprobs, const int32_t* dstart, int nprob, int nwg,
@@ -159,7 +161,9 @@ hipError_t launch_update(const UpdateProb* dprobs, const UpdateProb* hprobs, int
 // clusters in LDS (one lane per coordinate, `nc` coordinates per lane), so
 // each accumulator has a single writer and a fixed order.
 constexpr int kOwnWaves = 4;            // waves per workgroup
-constexpr int kOwnIters = 256;          // points per owner per chunk
+constexpr int kOwnIters = 256;          // points per owner per chunk (at most)
+constexpr int kOwnItersMin = 32;        // (at least: two batches of 16 in flight)
+constexpr int kOwnChunksWanted = 32;    // chunks a problem should have
 constexpr int kOwnWaveBytes = 34816;    // LDS per wave: accumulators + counts
 constexpr int kOwnCentreFloats = 4096;  // LDS staging of C_old (k*d floats)
 struct OwnShape {
@@ -187,9 +191,52 @@ inline int own_wave_bytes(int owners, int d, int k) {
   return (int)((((int64_t)owners * ((int64_t)k * d * 8 + (int64_t)k * 4)) + 15) / 16 * 16);
 }
 // points per chunk (one workgroup)
-inline int64_t own_chunk(const OwnShape& s) { return (int64_t)kOwnWaves * s.owners * kOwnIters; }
+inline int64_t own_chunk(const OwnShape& s, int iters) { return (int64_t)kOwnWaves * s.owners * iters; }
+// Points per owner per chunk: 256, halved (down to 32) while the problem has
+// fewer than kOwnChunksWanted chunks.  An owner's points are a chain of
+// dependent global-load batches, so a small problem cut in few long chunks
+// is latency-bound on a handful of workgroups; the choice depends on (n, d,
+// k) only, so results stay the same alone, batched and served.
+inline int own_iters(int64_t n, const OwnShape& s) {
+  int it = kOwnIters;
+  while (it > kOwnItersMin && (n + own_chunk(s, it) - 1) / own_chunk(s, it) < kOwnChunksWanted) it >>= 1;
+  return it;
+}
 // clusters per finalize workgroup
 constexpr int own_fin_clusters(int d) { return d >= 256 ? 1 : 256 / d; }
+// Persistent Lloyd rounds of small problems (d <= 32, k <= 64, owner-path
+// update): one launch runs every round of every problem in the list --
+// assignment tiles, update chunks, the reduction of the assignment partials
+// and the finalize of each cluster group, then per problem shift, SSE and
+// the stopping test -- with grid-wide waits between the phases.  Round r of a problem uses
+// a[r & 1] and u[r & 1] (centres C_old -> C_new of that round); every body is
+// the one of the one-launch-per-phase kernels, so the results are bitwise
+// theirs.
+struct RoundProb {
+  AssignProb a[2];
+  UpdateProb u[2];
+  ReduceProb red;
+  double* sse_hist;  // nullable: SSE of round r at [r]
+  double tol;        // > 0: stop after a round whose shift is below tol
+  int max_iter;      // >= 1
+  int nfin;          // finalize cluster groups
+  int wstride;       // LDS stride of the update's wave regions
+  int pad;
+};
+// Control words (device, zeroed before the launch): [0] wait arrivals,
+// [1] abort flag, [2, 2 + nprob) done flags, [2 + nprob, 2 + 2 nprob) rounds
+// run per problem.
+constexpr int round_ctl_words(int nprob) { return 2 + 2 * nprob; }
+constexpr int kRoundMaxProbs = 1024;  // problems of one persistent launch
+// tpre, cpre, fpre: prefixes of the problems' assignment tiles, update
+// chunks and finalize items (1 + nfin each).  Returns the runtime's error
+// when the grid cannot be co-resident; the caller then runs one launch per
+// phase.
+hipError_t launch_lloyd_rounds(int low, int xd, bool fallback, const RoundProb* dprobs, int nprob,
+                               const int32_t* tpre, const int32_t* cpre, const int32_t* fpre, int* ctl,
+                               int work_items, int lds_bytes, hipStream_t st);
+int small_lds_bytes(int xd, bool fallback);
+
 hipError_t launch_update_own_part(const UpdateProb* dprobs, const UpdateProb* hprobs, int nprob,
                                   const int32_t* dpre, hipStream_t st);
 hipError_t launch_update_own_fin(const UpdateProb* dprobs, const UpdateProb* hprobs, int nprob,
