@@ -191,6 +191,24 @@ int32_t kmeans_assign(km_context *ctx, const float *X, int64_t n, int32_t d,
                       int32_t *labels, float *mindist, double *sse,
                       km_stats *stats, void *stream, uint32_t flags);
 
+/* ---- one assignment pass with its per-pair fallback decisions --------------
+ * The pass of kmeans_assign (same labels, same counters), recording which
+ * pairs the reliability test eq:quantis-reliability-test sent to the
+ * high-precision fallback of eq:fallback-rule-mp (Algorithm alg:mp-dist):
+ * flagged [n*k] uint8, device, row-major by point, owned by the caller; the
+ * library clears it and writes 1 for every flagged pair, so that the count
+ * of ones equals stats->n_corrected.  A pass whose threshold flags every
+ * pair (alpha >= 2.5, run by the direct kernel) fills it with ones; the
+ * plain FP64 pass and a pass without a test leave it zero.  For diagnostics
+ * and tests: it shows where the expanded formula cancels.  mindist and the
+ * SSE are not produced (stats->sse_last is the refined SSE when stats is
+ * given).  Errors as kmeans_assign, KM_ERR_ARG for a NULL flagged. */
+int32_t kmeans_assign_flags(km_context *ctx, const float *X, int64_t n,
+                            int32_t d, const float *C, int32_t k,
+                            const km_precision *prec, int32_t *labels,
+                            uint8_t *flagged, km_stats *stats, void *stream,
+                            uint32_t flags);
+
 /* ---- one assignment pass without any allocation -----------------------------
  * For callers that cannot allocate device memory (code under HIP graph
  * capture, tight serving loops, harnesses that forbid hipMalloc): the same

@@ -19,7 +19,8 @@ __all__ = [
     "KM_ALPHA_PAPER_EQ", "KM_ALPHA_PAPER_ALG", "KM_ALPHA_EXPLICIT", "KM_ALPHA_NONE", "KM_ALPHA_HW",
     "KM_HIGH_FP64", "KM_HIGH_FP32", "KM_HIGH_LOW",
     "KM_SYNC", "KMeansError", "Precision", "Stats", "Problem", "library_path", "lib",
-    "Context", "kmeans_context_create", "kmeans_assign", "kmeans_assign_static", "kmeans_update",
+    "Context", "kmeans_context_create", "kmeans_assign", "kmeans_assign_static",
+    "kmeans_assign_flags", "kmeans_update",
     "kmeans_lloyd", "kmeans_lloyd_schedule", "kmeans_seed_pp", "kmeans_ari", "kmeans_ami",
     "kmeans_label_diff", "kmeans_solve_batch", "kmeans_pairwise", "kmeans_quantize",
     "kmeans_alpha", "kmeans_status_string", "Server", "kmeans_server_create",
@@ -104,6 +105,7 @@ def lib():
                 "kmeans_context_destroy": [P],
                 "kmeans_assign": [P, P, i64, i32, P, i32, PP, P, P, P, PS, P, u32],
                 "kmeans_assign_static": [P, P, i64, i32, P, i32, PP, P, P, P, PS, P, u32],
+                "kmeans_assign_flags": [P, P, i64, i32, P, i32, PP, P, P, PS, P, u32],
                 "kmeans_update": [P, P, i64, i32, P, i32, P, P, P, P, P, P, u32],
                 "kmeans_lloyd": [P, P, i64, i32, i32, P, i32, dbl, PP, P, P, P, PS, P, u32],
                 "kmeans_lloyd_schedule": [P, P, i64, i32, i32, P, i32, dbl, PP, PP, dbl, i32, P, P, P, PS,
@@ -303,6 +305,29 @@ def kmeans_assign_static(ctx: Context, X, C, prec=None, labels=None, mindist=Non
     by the caller)."""
     return kmeans_assign(ctx, X, C, prec, labels, mindist, sse, stats, stream, sync,
                          labels_hint, static=True)
+
+
+def kmeans_assign_flags(ctx: Context, X, C, prec=None, labels=None, flagged=None,
+                        stats=True, stream=None, sync=False, labels_hint=False):
+    """The assignment pass with its per-pair fallback decisions: returns
+    ``(labels, flagged (n,k) uint8, stats_dict_or_None)``."""
+    torch = _torch()
+    n, d = X.shape
+    k = C.shape[0]
+    if labels is None:
+        labels = torch.empty(n, dtype=torch.int32, device=X.device)
+    if flagged is None:
+        flagged = torch.empty((n, k), dtype=torch.uint8, device=X.device)
+    st = Stats() if stats else None
+    code = lib().kmeans_assign_flags(
+        ctx.handle, _dev_ptr(X, torch.float32, "X", n * d), n, d,
+        _dev_ptr(C, torch.float32, "C", k * d), k, _prec(prec),
+        _dev_ptr(labels, torch.int32, "labels", n),
+        _dev_ptr(flagged, torch.uint8, "flagged", n * k),
+        ct.byref(st) if st is not None else None, _stream_ptr(stream),
+        (KM_SYNC if sync else 0) | (KM_LABELS_HINT if labels_hint else 0))
+    _check(code, "kmeans_assign_flags")
+    return labels, flagged, (st.as_dict() if st is not None else None)
 
 
 def kmeans_pairwise(ctx: Context, X, C, prec=None, D=None, flagged=None,

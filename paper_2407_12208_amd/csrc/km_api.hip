@@ -754,6 +754,35 @@ int32_t kmeans_assign(km_context* ctx, const float* X, int64_t n, int32_t d, con
   return KM_OK;
 }
 
+int32_t kmeans_assign_flags(km_context* ctx, const float* X, int64_t n, int32_t d, const float* C, int32_t k,
+                            const km_precision* prec, int32_t* labels, uint8_t* flagged, km_stats* stats,
+                            void* stream, uint32_t flags) {
+  if (!ctx || !X || !C || !labels || !flagged) return KM_ERR_ARG;
+  km_precision p = precision_or_default(prec);
+  int32_t v = validate_precision(p);
+  if (v != KM_OK) return v;
+  v = check_shape(n, d, k, p);
+  if (v != KM_OK) return v;
+  hipStream_t st = (hipStream_t)stream;
+  KM_HIP(hipSetDevice(ctx->device));
+  WorkspaceUse ws_use(ctx, st);
+  KM_HIP(ws_use.err);
+  AssignPlan a = plan_assign(p, n, d, k);
+  Plan pl;
+  plan_pass(pl, a);
+  KM_HIP(ctx->arena.ensure(pl.bytes));
+  ctx->arena.reset();
+  PassBufs b = carve_pass(ctx->arena, a);
+  KM_HIP(zero_status_result(b.status, b.result, st));
+  // a pass routed to the direct kernel corrects every pair; otherwise the
+  // assignment kernels write a 1 for each pair their test flags
+  KM_HIP(launch_fill_bytes(flagged, n * (int64_t)k, a.route == Route::Direct64All ? 1 : 0, st));
+  KM_HIP(enqueue_pass(ctx, a, b, X, n, d, C, k, labels, nullptr, nullptr, 0, nullptr, flagged, stats != nullptr,
+                      (flags & KM_LABELS_HINT) != 0, st));
+  if (stats || (flags & KM_SYNC)) return finish_stats(ctx, b.result, stats, a, 0, st);
+  return KM_OK;
+}
+
 int32_t kmeans_assign_static(km_context* ctx, const float* X, int64_t n, int32_t d, const float* C,
                              int32_t k, const km_precision* prec, int32_t* labels, float* mindist,
                              double* sse, km_stats* stats, void* stream, uint32_t flags) {

@@ -801,6 +801,7 @@ k_assign_pipe(const AssignProb* __restrict__ probs, const int32_t* __restrict__ 
         if ((w + delta) + caj + delta < hx[cb]) bw[cb] = w - 2.0f * delta;
         if constexpr (kPreCorrect) {
           if ((w - delta) + caj - delta >= hx[cb] && (lane >> 5) == ((h >> 2) & 1)) {
+            if (P.flagged) as_global(P.flagged)[(p0 + pl) * (int64_t)P.k + h] = 1;  // diagnostic record
             const float df = (float)correct_pair<L>(P, P.X + (p0 + pl) * d, P.C + (int64_t)h * d, d);
             ncorr += 1;
             cd[cb] = df;
@@ -963,6 +964,7 @@ k_assign_pipe(const AssignProb* __restrict__ probs, const int32_t* __restrict__ 
             fm &= fm - 1;
             const int j = jb + acc_row(r, lane);
             if (j >= P.k) continue;
+            if (P.flagged) as_global(P.flagged)[(p0 + pl) * (int64_t)P.k + j] = 1;  // diagnostic record
             if (qn < kQueue) {
               s_q[qn * NT + tid] = j | (cb << 24);
               qn += 1;
@@ -1406,6 +1408,8 @@ assign_small_tile(const AssignProb& P, const int tile, SmallLds<XD, FALLBACK>& s
             const int r = __builtin_ctz(fm);
             fm &= fm - 1;
             sm.q[wave][pos++] = (lane & 31) | ((b * 32 + acc_row(r, lane)) << 5);
+            if (P.flagged)  // diagnostic record of the test's decision
+              as_global(P.flagged)[p * (int64_t)k + b * 32 + acc_row(r, lane)] = 1;
           }
           wave_lds_sync();
           for (int e = lane; e < total; e += 64) {
@@ -2084,6 +2088,19 @@ hipError_t launch_assign_direct64(bool cmp64, int arith, int mode, const AssignP
 // pass): one launch, and usable where a memset node is not.
 __global__ void __launch_bounds__(256) k_zero_words(uint32_t* __restrict__ p, int nwords) {
   for (int i = threadIdx.x; i < nwords; i += 256) as_global(p)[i] = 0u;
+}
+
+// Byte-exact fill of a device range (diagnostic flag maps).
+__global__ void __launch_bounds__(256) k_fill_bytes(uint8_t* __restrict__ p, int64_t count, uint8_t v) {
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < count; i += (int64_t)gridDim.x * 256)
+    as_global(p)[i] = v;
+}
+
+hipError_t launch_fill_bytes(void* p, int64_t count, uint8_t v, hipStream_t st) {
+  if (count <= 0) return hipSuccess;
+  const int64_t blocks = std::min<int64_t>((count + 255) / 256, 16384);
+  hipLaunchKernelGGL(k_fill_bytes, dim3((unsigned)blocks), dim3(256), 0, st, reinterpret_cast<uint8_t*>(p), count, v);
+  return hipGetLastError();
 }
 
 hipError_t launch_zero_words(void* p, size_t bytes, hipStream_t st) {

@@ -76,7 +76,8 @@ struct AssignProb {
   int32_t* labels;      // n
   float* mindist;       // n, nullable
   float* D;             // pairwise mode: n x k
-  uint8_t* flagged;     // pairwise mode: n x k, nullable
+  uint8_t* flagged;     // n x k, nullable: pairwise mode, every pair's flag; assignment
+                        // mode, 1 written for each pair the test sends to the fallback
   double* sse_part;     // one per workgroup of this problem
   unsigned long long* corr_part;
   int* status;
@@ -144,6 +145,7 @@ hipError_t launch_assign_direct64(bool cmp64, int arith, int mode, const AssignP
 hipError_t launch_reduce_parts(const ReduceProb* dprobs, int nprob, hipStream_t st);
 hipError_t launch_gather_results(const KResult* const* dsrc, int count, KResult* ddst, hipStream_t st);
 hipError_t launch_zero_words(void* p, size_t bytes, hipStream_t st);  // bytes rounded up to 4
+hipError_t launch_fill_bytes(void* p, int64_t count, uint8_t v, hipStream_t st);
 hipError_t launch_quantize(int low, const float* in, int64_t count, uint16_t* out, hipStream_t st);
 
 // centre update (km_update.hip)

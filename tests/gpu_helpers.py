@@ -19,6 +19,30 @@ import oracle
 DIST_RTOL = 1e-6
 
 
+def fp32_classes(Xs, C, alpha, dist):
+    """Per-pair classification for FP32 operands (quantisation is the
+    identity, so the oracle's O4 rounding does not apply): the FP32 bound A
+    of Theorem thm:dist-exp, the margin of the test against a band of
+    (1 + alpha) A plus the FP64 value's own rounding, and the error bound B
+    of the value the GPU reports.  Returns (cls, B): -1 surely flagged,
+    +1 surely kept, 0 ambiguous."""
+    u32 = oracle.unit_roundoff(2)
+    xn = (Xs.astype(np.float64) ** 2).sum(1)[:, None]
+    cn = (C.astype(np.float64) ** 2).sum(1)[None, :]
+    P = np.abs(Xs.astype(np.float64)) @ np.abs(C.astype(np.float64)).T
+    g = oracle.gamma(Xs.shape[1] + 4, 2 * u32)
+    A = g * (xn + cn + 2 * P)
+    B = A + 2 * u32 * dist
+    S = xn + cn
+    if alpha is None or alpha < 0:
+        return np.ones(dist.shape, dtype=np.int8), B
+    margin = dist - alpha * S
+    band = (1 + alpha) * A + 2 * u32 * dist
+    cls = np.where(margin < -band, -1, np.where(margin > band, 1, 0)).astype(np.int8)
+    B = np.where(cls == -1, 2 * u32 * dist, np.where(cls == 1, B, np.maximum(B, 2 * u32 * dist)))
+    return cls, B
+
+
 def check_assignment(X, C, fmt, alpha, labels, mindist, sse, n_corrected,
                      min_coverage=0.0, rows=None, check_sandwich=True):
     """Apply (i)-(iii).  ``rows`` restricts the check to a subset of points
@@ -41,20 +65,7 @@ def check_assignment(X, C, fmt, alpha, labels, mindist, sse, n_corrected,
             B = 2 * oracle.gamma(X.shape[1] + 2, oracle.unit_roundoff(3)) * dist
             cls = np.full(dist.shape, -1, dtype=np.int8)
         else:  # FP32 expanded formula: error bound of thm:dist-exp in FP32
-            xn = (Xs.astype(np.float64) ** 2).sum(1)[:, None]
-            cn = (C.astype(np.float64) ** 2).sum(1)[None, :]
-            P = np.abs(Xs.astype(np.float64)) @ np.abs(C.astype(np.float64)).T
-            g = oracle.gamma(X.shape[1] + 4, 2 * u32)
-            A = g * (xn + cn + 2 * P)
-            B = A + 2 * u32 * dist
-            S = xn + cn
-            if alpha is None or alpha < 0:
-                cls = np.ones(dist.shape, dtype=np.int8)
-            else:
-                margin = dist - alpha * S
-                band = (1 + alpha) * A + 2 * u32 * dist
-                cls = np.where(margin < -band, -1, np.where(margin > band, 1, 0)).astype(np.int8)
-                B = np.where(cls == -1, 2 * u32 * dist, np.where(cls == 1, B, np.maximum(B, 2 * u32 * dist)))
+            cls, B = fp32_classes(Xs, C, alpha, dist)
     m = len(rows)
     ii = np.arange(m)
     j1 = np.argmin(dist, axis=1)  # lowest index among exact minimisers
