@@ -10,6 +10,8 @@
 #include <map>
 #include <vector>
 
+#include <cstddef>
+
 #include "km_context.hpp"
 
 namespace km {
@@ -269,7 +271,8 @@ static hipError_t run_assign_dev(km_context_impl* ctx, const AssignPlan& shape, 
                                 (const int32_t*)ds, nprob, total_wg, st);
         break;
       }
-      e = launch_assign_mfma(shape.low, shape.DP, mode, shape.route == Route::Mfma, (const AssignProb*)dp,
+      e = launch_assign_mfma(shape.low, shape.DP, mode == 0 && shape.record ? 2 : mode, shape.route == Route::Mfma,
+                             (const AssignProb*)dp,
                              (const int32_t*)ds, nprob, total_wg, st);
       break;
     case Route::Direct64Exact:
@@ -768,6 +771,7 @@ int32_t kmeans_assign_flags(km_context* ctx, const float* X, int64_t n, int32_t 
   WorkspaceUse ws_use(ctx, st);
   KM_HIP(ws_use.err);
   AssignPlan a = plan_assign(p, n, d, k);
+  a.record = true;
   Plan pl;
   plan_pass(pl, a);
   KM_HIP(ctx->arena.ensure(pl.bytes));
@@ -895,6 +899,104 @@ int32_t kmeans_update(km_context* ctx, const float* X, int64_t n, int32_t d, con
 
 namespace km {
 
+// Descriptors of one Lloyd round, laid out for an upload of many rounds.
+struct RoundDesc {
+  alignas(16) PrepProb pp;
+  alignas(16) AssignProb ap;
+  alignas(16) ReduceProb rp;
+  alignas(16) UpdateProb up;
+};
+
+// Rounds of kmeans_lloyd with one launch per phase and the descriptors of up
+// to kRoundBlock rounds uploaded in one copy (one pass and one update
+// uploaded separately cost two copies per round, each a few microseconds on
+// the stream).  The launches and their arguments are those of enqueue_pass
+// and run_update.  Round r goes from C0/C1 (r even/odd) to the other
+// buffer; *done receives the rounds run (a positive tol reads the shift back
+// after every round).
+static hipError_t enqueue_phase_rounds(km_context_impl* ctx, const AssignPlan& a, const PassBufs& b,
+                                       const UpdateProb& u0, const float* X, int64_t n, int d, int k, float* C0,
+                                       float* C1, int32_t* labels, double* sse_hist, int max_iter, double tol,
+                                       int* done, hipStream_t st) {
+  constexpr int kRoundBlock = 128;
+  *done = 0;
+  const bool prep = uses_prep(a) && !(a.xd > 0);  // the small kernel prepares its centres itself
+  const int prep_wg = (a.k_pad + 3) / 4;          // one wave per centre
+  const bool own = u0.owners > 0;
+  // prefixes, the same every round: assignment, preparation, update
+  std::vector<int32_t> pre = {0, a.nwg, 0, prep_wg};
+  const size_t upd = pre.size();
+  if (own) {
+    const int J = own_fin_clusters(d);
+    for (int v : {u0.nchunk, (k + J - 1) / J}) pre.insert(pre.end(), {0, v});
+  } else {
+    const int chunkwg = (int)(((n + u0.chunk - 1) / u0.chunk + k + 3) / 4);
+    for (int v : {u0.ntiles, k, chunkwg, (k + 3) / 4, (u0.ntiles + 3) / 4}) pre.insert(pre.end(), {0, v});
+  }
+  const int32_t* dpre = static_cast<const int32_t*>(ctx->up.put(pre.data(), sizeof(int32_t) * pre.size(), st));
+  if (!dpre) return hipErrorOutOfMemory;
+  for (int r0 = 0; r0 < max_iter; r0 += kRoundBlock) {
+    const int r1 = std::min(max_iter, r0 + kRoundBlock);
+    std::vector<RoundDesc> rd((size_t)(r1 - r0));
+    for (int r = r0; r < r1; ++r) {
+      float* c_old = (r & 1) ? C1 : C0;
+      float* c_new = (r & 1) ? C0 : C1;
+      RoundDesc& q = rd[(size_t)(r - r0)];
+      q = RoundDesc{};
+      if (prep) {
+        q.pp.C = c_old;
+        q.pp.Cq = b.Cq;
+        q.pp.cinit = b.cinit;
+        q.pp.ca = b.ca;
+        q.pp.status = b.status;
+        q.pp.alpha = a.alpha_f;
+        q.pp.k = k;
+        q.pp.k_pad = a.k_pad;
+        q.pp.d = d;
+        q.pp.DP = a.DP;
+      }
+      // the SSE of a round's pass comes from the update, which reads every
+      // point's row against the centre it was assigned to
+      q.ap = pass_assign_prob(a, b, X, n, d, c_old, k, labels, nullptr, nullptr, nullptr, false, r > 0);
+      q.rp = pass_reduce_prob(b, n, k, nullptr, a.nwg);
+      q.up = u0;
+      q.up.C_old = c_old;
+      q.up.C_new = c_new;
+      q.up.sse_out = sse_hist ? sse_hist + r : nullptr;
+    }
+    char* dr = static_cast<char*>(ctx->up.put(rd.data(), sizeof(RoundDesc) * rd.size(), st));
+    if (!dr) return hipErrorOutOfMemory;
+    for (int r = r0; r < r1; ++r) {
+      char* dq = dr + sizeof(RoundDesc) * (size_t)(r - r0);
+      const RoundDesc& hq = rd[(size_t)(r - r0)];
+      const UpdateProb* dup = reinterpret_cast<const UpdateProb*>(dq + offsetof(RoundDesc, up));
+      hipError_t e = hipSuccess;
+      if (prep) e = launch_prep(a.low, reinterpret_cast<const PrepProb*>(dq + offsetof(RoundDesc, pp)), dpre + 2, 1,
+                                prep_wg, st);
+      if (e == hipSuccess) e = run_assign_dev(ctx, a, 0, dq + offsetof(RoundDesc, ap), dpre, 1, a.nwg, st);
+      if (e == hipSuccess)
+        e = launch_reduce_parts(reinterpret_cast<const ReduceProb*>(dq + offsetof(RoundDesc, rp)), 1, st);
+      if (e == hipSuccess) {
+        if (own) {
+          e = launch_update_own_part(dup, &hq.up, 1, dpre + upd, st);
+          if (e == hipSuccess) e = launch_update_own_fin(dup, &hq.up, 1, dpre + upd + 2, st);
+        } else {
+          e = launch_update(dup, &hq.up, 1, dpre + upd, st);
+        }
+      }
+      if (e != hipSuccess) return e;
+      *done = r + 1;
+      if (tol > 0.0) {
+        e = hipMemcpyAsync(ctx->h_scalar, &b.result->shift, sizeof(double), hipMemcpyDeviceToHost, st);
+        if (e == hipSuccess) e = hipStreamSynchronize(st);
+        if (e != hipSuccess) return e;
+        if (*ctx->h_scalar < tol) return hipSuccess;
+      }
+    }
+  }
+  return hipSuccess;
+}
+
 // Lloyd rounds that one persistent launch can run: the small-problem
 // assignment kernel and the owner path of the update.
 static bool rounds_fit(const AssignPlan& a, const UpdateProb& u) {
@@ -1018,24 +1120,11 @@ int32_t kmeans_lloyd(km_context* ctx, const float* X, int64_t n, int32_t d, int3
       if (it & 1) std::swap(cur, nxt);
     }
   }
-  for (; !ran && it < max_iter; ++it) {
-    // the SSE of a round's pass comes from the update, which reads every
-    // point's row against the centre it was assigned to
-    KM_HIP(enqueue_pass(ctx, a, b, X, n, d, cur, k, labels, nullptr, nullptr, 0, nullptr, nullptr, false,
-                        it > 0, st));
-    u.C_old = cur;
-    u.C_new = nxt;
-    u.sse_out = sse_hist ? sse_hist + it : nullptr;
-    KM_HIP(run_update(ctx, {u}, st));
-    std::swap(cur, nxt);
-    if (tol > 0.0) {
-      KM_HIP(hipMemcpyAsync(ctx->h_scalar, &b.result->shift, sizeof(double), hipMemcpyDeviceToHost, st));
-      KM_HIP(hipStreamSynchronize(st));
-      if (*ctx->h_scalar < tol) {
-        ++it;
-        break;
-      }
-    }
+  if (!ran && max_iter > 0) {
+    int done = 0;
+    KM_HIP(enqueue_phase_rounds(ctx, a, b, u, X, n, d, k, C_inout, Cw, labels, sse_hist, max_iter, tol, &done, st));
+    it = done;
+    if (it & 1) std::swap(cur, nxt);
   }
   KM_HIP(enqueue_pass(ctx, a, b, X, n, d, cur, k, labels, mindist, sse_hist ? sse_hist + it : nullptr, 0,
                       nullptr, nullptr, true, it > 0, st));

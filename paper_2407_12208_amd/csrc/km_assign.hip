@@ -584,7 +584,9 @@ k_assign_mfma(const AssignProb* __restrict__ probs, const int32_t* __restrict__ 
 // MFMA with a few VALU instructions).  The saved copy of a lane's best block
 // lives in LDS and is written only when the lane's best value improves.
 // ---------------------------------------------------------------------------
-template <class L, int DP, int NB, bool FALLBACK>
+// REC: also write a 1 into P.flagged for every flagged pair (diagnostic
+// launches only: the record's stores cost the sweep registers).
+template <class L, int DP, int NB, bool FALLBACK, bool REC = false>
 __global__ void __launch_bounds__(kPipeThreads, 1)
 k_assign_pipe(const AssignProb* __restrict__ probs, const int32_t* __restrict__ wg_start, int nprob) {
   using Cfg = AssignCfg<L, DP, NB, kPipeWaves>;
@@ -801,7 +803,7 @@ k_assign_pipe(const AssignProb* __restrict__ probs, const int32_t* __restrict__ 
         if ((w + delta) + caj + delta < hx[cb]) bw[cb] = w - 2.0f * delta;
         if constexpr (kPreCorrect) {
           if ((w - delta) + caj - delta >= hx[cb] && (lane >> 5) == ((h >> 2) & 1)) {
-            if (P.flagged) as_global(P.flagged)[(p0 + pl) * (int64_t)P.k + h] = 1;  // diagnostic record
+            if (REC && P.flagged) as_global(P.flagged)[(p0 + pl) * (int64_t)P.k + h] = 1;  // diagnostic record
             const float df = (float)correct_pair<L>(P, P.X + (p0 + pl) * d, P.C + (int64_t)h * d, d);
             ncorr += 1;
             cd[cb] = df;
@@ -820,6 +822,7 @@ k_assign_pipe(const AssignProb* __restrict__ probs, const int32_t* __restrict__ 
         const int j = e & 0xffffff;
         const int cbq = e >> 24;
         const int pl = pw + cbq * 32 + (lane & 31);
+        if (REC && P.flagged) as_global(P.flagged)[(p0 + pl) * (int64_t)P.k + j] = 1;  // diagnostic record
         const double dd = correct_pair<L>(P, P.X + (p0 + pl) * d, P.C + (int64_t)j * d, d);
         const float df = (float)dd;
         ncorr += 1;
@@ -964,11 +967,11 @@ k_assign_pipe(const AssignProb* __restrict__ probs, const int32_t* __restrict__ 
             fm &= fm - 1;
             const int j = jb + acc_row(r, lane);
             if (j >= P.k) continue;
-            if (P.flagged) as_global(P.flagged)[(p0 + pl) * (int64_t)P.k + j] = 1;  // diagnostic record
             if (qn < kQueue) {
               s_q[qn * NT + tid] = j | (cb << 24);
               qn += 1;
             } else {  // queue full (dense flags): correct this pair now
+              if (REC && P.flagged) as_global(P.flagged)[(p0 + pl) * (int64_t)P.k + j] = 1;  // diagnostic record
               const float df = (float)correct_pair<L>(P, P.X + (p0 + pl) * d, P.C + (int64_t)j * d, d);
               ncorr += 1;
               if (df < cd[cb] || (df == cd[cb] && j < cj[cb])) {
@@ -1936,8 +1939,11 @@ hipError_t launch_prep(int low, const PrepProb* dprobs, const int32_t* dstart, i
 template <class L, int DP, int NB>
 static hipError_t launch_mfma_t(int mode, bool fallback, const AssignProb* dprobs, const int32_t* dstart,
                                 int nprob, int nwg, hipStream_t st) {
-  if (mode == 0) {
-    if (fallback)
+  if (mode == 0 || mode == 2) {  // 2: assignment recording the flagged pairs
+    if (fallback && mode == 2)
+      hipLaunchKernelGGL((k_assign_pipe<L, DP, NB, true, true>), dim3(nwg), dim3(kPipeThreads), 0, st, dprobs, dstart,
+                         nprob);
+    else if (fallback)
       hipLaunchKernelGGL((k_assign_pipe<L, DP, NB, true>), dim3(nwg), dim3(kPipeThreads), 0, st, dprobs, dstart, nprob);
     else
       hipLaunchKernelGGL((k_assign_pipe<L, DP, NB, false>), dim3(nwg), dim3(kPipeThreads), 0, st, dprobs, dstart, nprob);

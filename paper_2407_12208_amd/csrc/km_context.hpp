@@ -154,6 +154,7 @@ struct AssignPlan {
   float alpha_f;    // alpha as applied (FP32)
   float oma;        // 1 - alpha (FP32)
   double alpha_used;
+  bool record = false;  // the large kernel writes the flagged pairs (diagnostics)
 };
 AssignPlan plan_assign(const km_precision& p, int64_t n, int d, int k);
 void set_small_sweep(AssignPlan& a, int64_t n, int64_t launch_points);

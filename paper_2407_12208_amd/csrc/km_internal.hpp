@@ -135,6 +135,7 @@ struct UpdateProb {
 
 hipError_t launch_prep(int low, const PrepProb* dprobs, const int32_t* dstart, int nprob, int nwg,
                        hipStream_t st);
+// mode: 0 assignment, 1 materialised pairs, 2 assignment writing P.flagged
 hipError_t launch_assign_mfma(int low, int DP, int mode, bool fallback, const AssignProb* dprobs,
                               const int32_t* dstart, int nprob, int nwg, hipStream_t st);
 hipError_t launch_assign_small(int low, int xd, bool fallback, const AssignProb* dprobs, const int32_t* dstart,
