@@ -911,7 +911,8 @@ struct RoundDesc {
 // to kRoundBlock rounds uploaded in one copy (one pass and one update
 // uploaded separately cost two copies per round, each a few microseconds on
 // the stream).  The launches and their arguments are those of enqueue_pass
-// and run_update.  Round r goes from C0/C1 (r even/odd) to the other
+// and run_update (for an owner-path update the partial reduction of the
+// pass runs in the launch of the shift).  Round r goes from C0/C1 (r even/odd) to the other
 // buffer; *done receives the rounds run (a positive tol reads the shift back
 // after every round).
 static hipError_t enqueue_phase_rounds(km_context_impl* ctx, const AssignPlan& a, const PassBufs& b,
@@ -973,15 +974,16 @@ static hipError_t enqueue_phase_rounds(km_context_impl* ctx, const AssignPlan& a
       hipError_t e = hipSuccess;
       if (prep) e = launch_prep(a.low, reinterpret_cast<const PrepProb*>(dq + offsetof(RoundDesc, pp)), dpre + 2, 1,
                                 prep_wg, st);
+      const ReduceProb* drp = reinterpret_cast<const ReduceProb*>(dq + offsetof(RoundDesc, rp));
       if (e == hipSuccess) e = run_assign_dev(ctx, a, 0, dq + offsetof(RoundDesc, ap), dpre, 1, a.nwg, st);
-      if (e == hipSuccess)
-        e = launch_reduce_parts(reinterpret_cast<const ReduceProb*>(dq + offsetof(RoundDesc, rp)), 1, st);
       if (e == hipSuccess) {
-        if (own) {
+        if (own) {  // the partial reduction joins the shift launch at the end
           e = launch_update_own_part(dup, &hq.up, 1, dpre + upd, st);
-          if (e == hipSuccess) e = launch_update_own_fin(dup, &hq.up, 1, dpre + upd + 2, st);
+          if (e == hipSuccess) e = launch_update_own_fin(dup, &hq.up, 1, dpre + upd + 2, st, false);
+          if (e == hipSuccess) e = launch_round_tail(drp, dup, st);
         } else {
-          e = launch_update(dup, &hq.up, 1, dpre + upd, st);
+          e = launch_reduce_parts(drp, 1, st);
+          if (e == hipSuccess) e = launch_update(dup, &hq.up, 1, dpre + upd, st);
         }
       }
       if (e != hipSuccess) return e;

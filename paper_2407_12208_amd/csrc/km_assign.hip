@@ -1903,6 +1903,23 @@ k_assign_direct64(const AssignProb* __restrict__ probs, const int32_t* __restric
 // result record (SSE, corrected pairs, status).
 // ---------------------------------------------------------------------------
 
+// End of a Lloyd round of one owner-path problem, in one launch: the
+// pass's partial reduction, then the update's shift and SSE (the bodies of
+// k_reduce_parts and k_upd_own_shift, in that order).
+__global__ void __launch_bounds__(256) k_round_tail(const ReduceProb* __restrict__ rp,
+                                                    const UpdateProb* __restrict__ up) {
+  __shared__ double ss[256];
+  __shared__ unsigned long long sc[256];
+  reduce_parts_prob(*rp, ss, sc);
+  __syncthreads();
+  own_shift_prob(*up, up->sse_out, ss);
+}
+
+hipError_t launch_round_tail(const ReduceProb* drp, const UpdateProb* dup, hipStream_t st) {
+  hipLaunchKernelGGL(k_round_tail, dim3(1), dim3(256), 0, st, drp, dup);
+  return hipGetLastError();
+}
+
 __global__ void __launch_bounds__(256)
 k_reduce_parts(const ReduceProb* __restrict__ probs) {
   __shared__ double ss[256];

@@ -242,7 +242,11 @@ int small_lds_bytes(int xd, bool fallback);
 
 hipError_t launch_update_own_part(const UpdateProb* dprobs, const UpdateProb* hprobs, int nprob,
                                   const int32_t* dpre, hipStream_t st);
+// shift = false leaves the shift and SSE to the caller (launch_round_tail)
 hipError_t launch_update_own_fin(const UpdateProb* dprobs, const UpdateProb* hprobs, int nprob,
-                                 const int32_t* dpre, hipStream_t st);
+                                 const int32_t* dpre, hipStream_t st, bool shift = true);
+// One problem's partial reduction (as k_reduce_parts) then owner-path shift
+// and SSE (as k_upd_own_shift), in one launch.
+hipError_t launch_round_tail(const ReduceProb* drp, const UpdateProb* dup, hipStream_t st);
 
 }  // namespace km

@@ -526,7 +526,7 @@ hipError_t launch_update_own_part(const UpdateProb* dprobs, const UpdateProb* hp
 // Finalize and shift launches over all owner-path problems of a round; dpre
 // is the device finalize prefix.
 hipError_t launch_update_own_fin(const UpdateProb* dprobs, const UpdateProb* hprobs, int nprob,
-                                 const int32_t* dpre, hipStream_t st) {
+                                 const int32_t* dpre, hipStream_t st, bool shift) {
   if (nprob < 1) return hipSuccess;
   int fin = 0;
   for (int i = 0; i < nprob; ++i) {
@@ -534,7 +534,7 @@ hipError_t launch_update_own_fin(const UpdateProb* dprobs, const UpdateProb* hpr
     fin += (hprobs[i].k + J - 1) / J;
   }
   hipLaunchKernelGGL(k_upd_own_fin, dim3(fin), dim3(256), 0, st, dprobs, dpre, nprob);
-  hipLaunchKernelGGL(k_upd_own_shift, dim3(nprob), dim3(256), 0, st, dprobs);
+  if (shift) hipLaunchKernelGGL(k_upd_own_shift, dim3(nprob), dim3(256), 0, st, dprobs);
   return hipGetLastError();
 }
 
