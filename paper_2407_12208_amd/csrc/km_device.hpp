@@ -143,13 +143,32 @@ __device__ __noinline__ double sqdist64_call(const float* __restrict__ x,
 // ---------------------------------------------------------------------------
 constexpr int kHigh64 = 0, kHigh32 = 1, kHighLow = 2;
 
+// f(x_l, c_l) for l = 0 .. d-1 in index order; the rows are read four
+// coordinates per 16-byte load when both are 16-byte aligned and d is a
+// multiple of 4 (rows in global memory or in LDS).
+template <class F>
+__device__ __forceinline__ void for_coords(const float* x, const float* c, int d, F&& f) {
+  int l = 0;
+  if ((((uintptr_t)x | (uintptr_t)c) & 15) == 0 && (d & 3) == 0) {
+    for (; l < d; l += 4) {
+      const f32x4 a = *reinterpret_cast<const f32x4*>(x + l);
+      const f32x4 b = *reinterpret_cast<const f32x4*>(c + l);
+      f(a.x, b.x);
+      f(a.y, b.y);
+      f(a.z, b.z);
+      f(a.w, b.w);
+    }
+  }
+  for (; l < d; ++l) f(x[l], c[l]);
+}
+
 // FP32 direct formula, coordinates in index order.
 __device__ inline float sqdist32(const float* x, const float* c, int d) {
   float s = 0.0f;
-  for (int l = 0; l < d; ++l) {
-    const float t = x[l] - c[l];
+  for_coords(x, c, d, [&](float a, float b) {
+    const float t = a - b;
     s = __builtin_fmaf(t, t, s);
-  }
+  });
   return s;
 }
 
@@ -157,10 +176,10 @@ __device__ inline float sqdist32(const float* x, const float* c, int d) {
 // half-precision subtraction and fused multiply-add round once each.
 __device__ inline float sqdist16(const float* x, const float* c, int d) {
   _Float16 s = (_Float16)0.0f;
-  for (int l = 0; l < d; ++l) {
-    const _Float16 t = (_Float16)x[l] - (_Float16)c[l];
+  for_coords(x, c, d, [&](float a, float b) {
+    const _Float16 t = (_Float16)a - (_Float16)b;
     s = __builtin_fmaf16(t, t, s);
-  }
+  });
   return (float)s;
 }
 
@@ -204,10 +223,10 @@ __device__ inline float bf16_fma(float a, float b, float c) {
 // bfloat16 direct formula on x~ = RNE_bf16(x), c~ = RNE_bf16(c).
 __device__ inline float sqdistbf16(const float* x, const float* c, int d) {
   float s = 0.0f;
-  for (int l = 0; l < d; ++l) {
-    const float t = bf16_sub((float)(__bf16)x[l], (float)(__bf16)c[l]);
+  for_coords(x, c, d, [&](float a, float b) {
+    const float t = bf16_sub((float)(__bf16)a, (float)(__bf16)b);
     s = bf16_fma(t, t, s);
-  }
+  });
   return s;
 }
 
