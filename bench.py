@@ -309,11 +309,11 @@ def batch_bench(km, ctx, torch, W, np, count=256, iters=30):
     del insts
     prec = km.Precision(km.KM_LOW_FP16)
 
-    def batched():
+    def batched(round_launch=False):
         items = [km.BatchItem(X=X, C=C0.clone(), max_iter=iters) for X, C0 in zip(Xs, C0s)]
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        km.kmeans_solve_batch(ctx, items, prec, with_sse=False)
+        km.kmeans_solve_batch(ctx, items, prec, with_sse=False, round_launch=round_launch)
         torch.cuda.synchronize()
         return time.perf_counter() - t0, [it.labels for it in items]
 
@@ -332,6 +332,10 @@ def batch_bench(km, ctx, torch, W, np, count=256, iters=30):
     tb, lb = batched()
     ts, ls = one_by_one()
     same = all(bool(torch.equal(a, b)) for a, b in zip(lb, ls))
+    # the same batch with every problem's rounds in persistent launches
+    batched(round_launch=True)
+    tp, lp = batched(round_launch=True)
+    same_p = all(bool(torch.equal(a, b)) for a, b in zip(lp, ls))
     passes = iters + 1
     # algorithmic bytes of an assignment pass: read X once, write the labels
     alg_bytes = float(total_n) * (4 * d + 4) * passes
@@ -339,6 +343,7 @@ def batch_bench(km, ctx, torch, W, np, count=256, iters=30):
            "batched_s": tb, "one_by_one_s": ts, "speedup": ts / tb,
            "batched_solves_per_s": count / tb, "one_by_one_solves_per_s": count / ts,
            "labels_identical": same,
+           "batched_round_launch_s": tp, "round_launch_labels_identical": same_p,
            "batched_assign_bytes_GBps": alg_bytes / tb / 1e9,
            "batched_frac_of_hbm_peak": alg_bytes / tb / 1e9 / HBM_PEAK_GBS,
            # the sweep-length tuner's choice for this launch (made by the

@@ -136,10 +136,10 @@ typedef struct km_stats {
 #define KM_LABELS_HINT 2u /* kmeans_assign: labels holds an earlier assignment
                              (e.g. the previous Lloyd round); it only seeds
                              the search, the results are the same */
-#define KM_ROUND_LAUNCH 4u /* kmeans_lloyd: run all rounds in one persistent
-                              launch where the shape allows it (see
-                              kmeans_lloyd); the results are bitwise the
-                              same as with one launch per phase */
+#define KM_ROUND_LAUNCH 4u /* kmeans_lloyd, kmeans_solve_batch: run all rounds
+                              in one persistent launch where the shape allows
+                              it (see kmeans_lloyd); the results are bitwise
+                              the same as with one launch per phase */
 
 typedef struct km_context km_context;
 typedef struct km_server km_server;
@@ -337,7 +337,11 @@ int32_t kmeans_label_diff(const int32_t *labels_a, const int32_t *labels_b,
  * phase of a Lloyd round is one launch over a work list that spans all
  * problems, so small problems share the GPU.  Every problem's arithmetic is
  * identical to a kmeans_lloyd call on it alone (bitwise).  Per-problem tol
- * stopping is honoured at round granularity. */
+ * stopping is honoured at round granularity.  With KM_ROUND_LAUNCH in flags
+ * the problems that kmeans_lloyd's persistent launch serves run all their
+ * remaining rounds (after any sweep-length tuning rounds) in one persistent
+ * launch per kernel shape, each with its own max_iter and tol; results are
+ * bitwise the same. */
 int32_t kmeans_solve_batch(km_context *ctx, km_problem *probs, int32_t count,
                            const km_precision *prec, void *stream,
                            uint32_t flags);

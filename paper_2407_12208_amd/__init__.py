@@ -519,7 +519,7 @@ class BatchItem:
 
 
 def kmeans_solve_batch(ctx: Context, items, prec=None, stream=None, sync=True,
-                       with_mindist=False, with_sse=True):
+                       with_mindist=False, with_sse=True, round_launch=False):
     """Solves a list of BatchItem (device tensors) in one set of launches.
     Fills labels / mindist / sse_hist on each item; returns per-item stats."""
     torch = _torch()
@@ -548,7 +548,8 @@ def kmeans_solve_batch(ctx: Context, items, prec=None, stream=None, sync=True,
         arr[i].tol = float(it.tol)
         arr[i].stats = ct.pointer(stats[i])
     code = lib().kmeans_solve_batch(ctx.handle, arr, len(items), _prec(prec),
-                                    _stream_ptr(stream), KM_SYNC if sync else 0)
+                                    _stream_ptr(stream),
+                                    (KM_SYNC if sync else 0) | (KM_ROUND_LAUNCH if round_launch else 0))
     _check(code, "kmeans_solve_batch")
     return [s.as_dict() for s in stats]
 

@@ -1383,6 +1383,98 @@ hipError_t enqueue_batch_round(km_context_impl* ctx, std::vector<BatchState*>& a
   return hipSuccess;
 }
 
+// Every remaining round of the listed problems that one persistent launch
+// can run (rounds_fit), one cooperative launch per kernel shape (row
+// capacity, threshold on/off), at most kRoundMaxProbs problems each.  The
+// per-round descriptors are those of enqueue_batch_round; a problem's rounds
+// are its own (max_iter, tol), so each gets the bits it gets alone.  Problems
+// handled are marked done with their rounds and centre buffer; a launch the
+// runtime refuses leaves its problems to the caller's per-phase rounds.
+static hipError_t enqueue_batch_rounds(km_context_impl* ctx, std::vector<BatchState>& S, int* ctl,
+                                       hipStream_t st) {
+  std::map<std::pair<int, int>, std::vector<BatchState*>> groups;
+  for (auto& s : S)
+    if (!s.done && s.it < s.prob->max_iter && rounds_fit(s.plan, s.upd))
+      groups[{s.plan.xd, s.plan.route == Route::Mfma ? 1 : 0}].push_back(&s);
+  for (auto& g : groups) {
+    for (size_t g0 = 0; g0 < g.second.size(); g0 += kRoundMaxProbs) {
+      const size_t g1 = std::min(g.second.size(), g0 + (size_t)kRoundMaxProbs);
+      std::vector<BatchState*> list(g.second.begin() + g0, g.second.begin() + g1);
+      const int np = (int)list.size();
+      std::vector<RoundProb> R((size_t)np);
+      std::vector<int> tiles(np), chunks(np), fins(np);
+      int lds = 0, work = 0;
+      bool need_tol = false;
+      for (int i = 0; i < np; ++i) {
+        BatchState& b = *list[i];
+        const km_problem& q = *b.prob;
+        RoundProb& r = R[i];
+        for (int par = 0; par < 2; ++par) {
+          float* c_old = par == 0 ? b.cur : b.nxt;
+          float* c_new = par == 0 ? b.nxt : b.cur;
+          r.a[par] = pass_assign_prob(b.plan, b.bufs, q.X, q.n, q.d, c_old, q.k, q.labels, nullptr, nullptr,
+                                      nullptr, false, false);
+          r.u[par] = b.upd;
+          r.u[par].C_old = c_old;
+          r.u[par].C_new = c_new;
+          r.u[par].sse_out = nullptr;
+        }
+        r.red = pass_reduce_prob(b.bufs, q.n, q.k, nullptr, b.plan.nwg);
+        r.sse_hist = q.sse_hist ? q.sse_hist + b.it : nullptr;
+        r.tol = q.tol;
+        r.max_iter = q.max_iter - b.it;
+        const int J = own_fin_clusters(q.d);
+        r.nfin = (q.k + J - 1) / J;
+        r.wstride = std::max(16, own_wave_bytes(b.upd.owners, q.d, q.k));
+        tiles[i] = b.plan.nwg;
+        chunks[i] = b.upd.nchunk;
+        fins[i] = 1 + r.nfin;
+        lds = std::max(lds, kOwnWaves * r.wstride + 4 * q.k * q.d);
+        work = std::max(work, std::max(b.plan.nwg, b.upd.nchunk));
+        need_tol |= q.tol > 0.0;
+      }
+      std::vector<int32_t> tpre = prefix(tiles), cpre = prefix(chunks), fpre = prefix(fins);
+      work = std::max(work, std::max(std::max(tpre.back(), cpre.back()), fpre.back()));
+      const bool fb = g.first.second != 0;
+      lds = std::max(lds, small_lds_bytes(g.first.first, fb));
+      Pack pk;
+      const size_t o_r = pk.add(R.data(), sizeof(RoundProb) * R.size());
+      const size_t o_t = pk.add(tpre.data(), sizeof(int32_t) * tpre.size());
+      const size_t o_c = pk.add(cpre.data(), sizeof(int32_t) * cpre.size());
+      const size_t o_f = pk.add(fpre.data(), sizeof(int32_t) * fpre.size());
+      char* dv = pk.upload(ctx, st);
+      if (!dv) return hipErrorOutOfMemory;
+      hipError_t e = launch_zero_words(ctl, sizeof(int) * (size_t)round_ctl_words(np), st);
+      if (e != hipSuccess) return e;
+      e = launch_lloyd_rounds(list[0]->plan.low, g.first.first, fb, (const RoundProb*)(dv + o_r), np,
+                              (const int32_t*)(dv + o_t), (const int32_t*)(dv + o_c), (const int32_t*)(dv + o_f),
+                              ctl, work, lds, st);
+      if (e != hipSuccess) {  // not co-resident: per-phase rounds instead
+        (void)hipGetLastError();
+        continue;
+      }
+      std::vector<int> rounds((size_t)np);
+      if (need_tol) {  // the rounds run are known on the device only
+        int* h = reinterpret_cast<int*>(ctx->h_result);
+        e = hipMemcpyAsync(h, ctl, sizeof(int) * (size_t)round_ctl_words(np), hipMemcpyDeviceToHost, st);
+        if (e == hipSuccess) e = hipStreamSynchronize(st);
+        if (e != hipSuccess) return e;
+        if (h[1] != 0) return hipErrorLaunchFailure;
+        for (int i = 0; i < np; ++i) rounds[i] = h[2 + np + i];
+      } else {
+        for (int i = 0; i < np; ++i) rounds[i] = list[i]->prob->max_iter - list[i]->it;
+      }
+      for (int i = 0; i < np; ++i) {
+        BatchState& b = *list[i];
+        b.it += rounds[i];
+        if (rounds[i] & 1) std::swap(b.cur, b.nxt);
+        b.done = true;
+      }
+    }
+  }
+  return hipSuccess;
+}
+
 }  // namespace km
 
 extern "C" int32_t kmeans_solve_batch(km_context* ctx, km_problem* probs, int32_t count,
@@ -1421,6 +1513,8 @@ extern "C" int32_t kmeans_solve_batch(km_context* ctx, km_problem* probs, int32_
     plan_update(pl, probs[i].n, probs[i].d, probs[i].k);
     pl.add<float>((size_t)probs[i].k * probs[i].d);
   }
+  bool round_launch = (flags & KM_ROUND_LAUNCH) != 0;
+  if (round_launch) pl.add<int>((size_t)round_ctl_words(std::min(count, kRoundMaxProbs)));
   KM_HIP(ctx->arena.ensure(pl.bytes));
   ctx->arena.reset();
   KResult* results = nullptr;
@@ -1438,6 +1532,8 @@ extern "C" int32_t kmeans_solve_batch(km_context* ctx, km_problem* probs, int32_
     s.done = s.prob->max_iter == 0;
   }
   (void)results;
+  int* round_ctl = round_launch ? ctx->arena.take<int>((size_t)round_ctl_words(std::min(count, kRoundMaxProbs)))
+                                : nullptr;
   bool need_tol = false;
   for (int i = 0; i < count; ++i) need_tol |= probs[i].tol > 0.0;
   // Sweep-length tuner of the small-problem launches: the first rounds run
@@ -1508,6 +1604,11 @@ extern "C" int32_t kmeans_solve_batch(km_context* ctx, km_problem* probs, int32_
     for (auto& s : S)
       if (!s.done) act.push_back(&s);
     if (act.empty()) break;
+    if (round_launch && !tune) {  // the remaining rounds in persistent launches
+      round_launch = false;
+      KM_HIP(enqueue_batch_rounds(ctx, S, round_ctl, st));
+      continue;
+    }
     if (tune && round < kTuneN) apply_gpw(kTuneGpw[round]);
     KM_HIP(enqueue_batch_round(ctx, act, st));
     if (tune && round < kTuneN) ev_mark[round + 1] = ctx->ev_used;

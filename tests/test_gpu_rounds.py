@@ -137,3 +137,30 @@ def test_rounds_match_oracle(ctx):
     sp = np.spacing(np.maximum(np.abs(C), np.abs(ref["C"])).astype(np.float32))
     assert (np.abs(C.astype(np.float64) - ref["C"]) <= sp).all()
     assert st["iters"] == T and st["data_status"] == 0
+
+
+def _batch(ctx, inst, prec, round_launch):
+    items = [km.BatchItem(X=dev(X), C=dev(C0), max_iter=T, tol=tol) for X, C0, T, tol in inst]
+    stats = km.kmeans_solve_batch(ctx, items, prec, with_mindist=True, round_launch=round_launch)
+    return [(host(it.C), host(it.labels), host(it.mindist), host(it.sse_hist), st)
+            for it, st in zip(items, stats)]
+
+
+@pytest.mark.parametrize("prec", [FP16, BF16_HW])
+def test_batch_round_launch_equals_phase_launches(ctx, prec):
+    # uneven problems: segmentation-shaped (d = 5, several k), blobs at d = 8,
+    # 16 and 32 (three kernel shapes, so several persistent launches), a
+    # tolerance stop, different round counts, and a d = 64 problem that the
+    # persistent launch does not serve (it keeps its per-phase rounds)
+    inst = []
+    for r in range(3):
+        X, _ = W.segmentation_instance(900 + r, hw_range=(64, 160))
+        inst.append((X, W.init_centroids(X, 4 + 19 * r, 910 + r), 5 + r, 0.0))
+    for i, (n, d, k) in enumerate([(7_001, 8, 33), (4_096, 16, 64), (20_000, 32, 16), (3_000, 64, 20)]):
+        X, _, _ = W.blobs(n, d, k, seed=920 + i)
+        inst.append((X, W.init_centroids(X, k, 930 + i), 6, 1e-4 if i == 2 else 0.0))
+    a = _batch(ctx, inst, prec, True)
+    b = _batch(ctx, inst, prec, False)
+    for i, (x, y) in enumerate(zip(a, b)):
+        print("problem", i, "iters", x[4]["iters"], flush=True)
+        assert_same(x, y)
