@@ -283,6 +283,11 @@ def test_batch_segmentation_vs_oracle(ctx):
         assert host(it.sse_hist)[0] == pytest.approx(ref["sse_hist"][0], rel=1e-6)
         check_assignment(b["X"], host(it.C), 0, st["alpha_used"], host(it.labels), None,
                          None, None, min_coverage=0.9)
+        # the final pass's SSE is the oracle's SSE of the returned labels
+        # against the returned centres
+        final = oracle.sse_labels(b["X"], host(it.C), host(it.labels))
+        assert host(it.sse_hist)[-1] == pytest.approx(final, rel=1e-6)
+        assert st["sse_last"] == pytest.approx(final, rel=1e-6)
 
 
 def test_batch_equals_alone_when_the_launch_sweeps_longer(ctx):
