@@ -67,3 +67,19 @@ def test_host_only_helpers():
         with pytest.raises(km.KMeansError) as e:
             km.Context(0)
         assert e.value.code == -5
+
+
+def test_binding_constants_match_the_header():
+    # every flag (#define KM_x <n>u) and enumerator (KM_x = <n>) the header
+    # gives a value that the binding also names carries the same value there
+    import paper_2407_12208_amd as km
+    src = re.sub(r"/\*.*?\*/", "", open(HEADER).read(), flags=re.S)
+    vals = {m.group(1): int(m.group(2)) for m in re.finditer(r"#define\s+(KM_[A-Z0-9_]+)\s+(\d+)u\b", src)}
+    vals.update({m.group(1): int(m.group(2))
+                 for m in re.finditer(r"\b(KM_[A-Z0-9_]+)\s*=\s*(-?\d+)", src)})
+    assert {"KM_SYNC", "KM_LABELS_HINT", "KM_ROUND_LAUNCH", "KM_LOW_FP16", "KM_ALPHA_HW",
+            "KM_HIGH_LOW", "KM_OK", "KM_PENDING"} <= set(vals)
+    named = [n for n in vals if hasattr(km, n)]
+    assert len(named) >= 16
+    for n in named:
+        assert getattr(km, n) == vals[n], n
