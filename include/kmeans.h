@@ -263,7 +263,9 @@ int32_t kmeans_update(km_context *ctx, const float *X, int64_t n, int32_t d,
  * costs no read per round and the host issues one launch per solve.  The
  * results are bitwise those of one launch per phase (the default, which is
  * the faster of the two when tol <= 0).  KM_ERR_DEVICE if such a wait ever
- * gives up (it never should; the launch then ends instead of hanging).
+ * gives up (it never should; the launch then ends instead of hanging; the
+ * KM_ROUND_SPIN_LIMIT environment variable caps a wait's polls, for tests
+ * of that path).
  * Normalisation of the data (first line of the algorithm) is the caller's. */
 int32_t kmeans_lloyd(km_context *ctx, const float *X, int64_t n, int32_t d,
                      int32_t k, float *C_inout, int32_t max_iter, double tol,

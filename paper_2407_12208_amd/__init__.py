@@ -35,6 +35,8 @@ KM_SYNC = 1
 KM_LABELS_HINT = 2
 KM_ROUND_LAUNCH = 4
 KM_OK, KM_PENDING = 0, 1
+(KM_ERR_ARG, KM_ERR_RANGE, KM_ERR_NONFINITE, KM_ERR_OOM, KM_ERR_DEVICE, KM_ERR_NOTFOUND,
+ KM_ERR_CANCELLED, KM_ERR_UNSUPPORTED) = -1, -2, -3, -4, -5, -6, -7, -8
 _STATUS_NAMES = {
     0: "KM_OK", 1: "KM_PENDING", -1: "KM_ERR_ARG", -2: "KM_ERR_RANGE",
     -3: "KM_ERR_NONFINITE", -4: "KM_ERR_OOM", -5: "KM_ERR_DEVICE",

@@ -2,6 +2,7 @@
 // workspace planning and the launch sequences of one assignment pass, one
 // centre update, Lloyd's loop and batched solves.
 #include <math.h>
+#include <stdlib.h>
 #include <string.h>
 
 #include <algorithm>
@@ -999,6 +1000,17 @@ static hipError_t enqueue_phase_rounds(km_context_impl* ctx, const AssignPlan& a
   return hipSuccess;
 }
 
+// Polls after which a grid-wide wait of the persistent launch gives up:
+// kSyncSpins, or KM_ROUND_SPIN_LIMIT from the environment (a small value
+// forces the give-up path in tests; the launch still ends and the call
+// reports KM_ERR_DEVICE).
+static unsigned round_spin_limit() {
+  const char* e = getenv("KM_ROUND_SPIN_LIMIT");
+  if (!e || !*e) return kSyncSpins;
+  const unsigned long v = strtoul(e, nullptr, 10);
+  return v >= 1 && v <= kSyncSpins ? (unsigned)v : kSyncSpins;
+}
+
 // Lloyd rounds that one persistent launch can run: the small-problem
 // assignment kernel and the owner path of the update.
 static bool rounds_fit(const AssignPlan& a, const UpdateProb& u) {
@@ -1056,7 +1068,7 @@ static hipError_t enqueue_rounds(km_context_impl* ctx, const AssignPlan& a, cons
   }
   e = launch_lloyd_rounds(a.low, a.xd, fb, (const RoundProb*)(dv + o_r), 1, (const int32_t*)(dv + o_t),
                           (const int32_t*)(dv + o_c), (const int32_t*)(dv + o_f), ctl,
-                          std::max(a.nwg, u0.nchunk), lds, st);
+                          std::max(a.nwg, u0.nchunk), lds, round_spin_limit(), st);
   if (e != hipSuccess) {
     (void)hipGetLastError();
     return hipSuccess;
@@ -1448,7 +1460,7 @@ static hipError_t enqueue_batch_rounds(km_context_impl* ctx, std::vector<BatchSt
       if (e != hipSuccess) return e;
       e = launch_lloyd_rounds(list[0]->plan.low, g.first.first, fb, (const RoundProb*)(dv + o_r), np,
                               (const int32_t*)(dv + o_t), (const int32_t*)(dv + o_c), (const int32_t*)(dv + o_f),
-                              ctl, work, lds, st);
+                              ctl, work, lds, round_spin_limit(), st);
       if (e != hipSuccess) {  // not co-resident: per-phase rounds instead
         (void)hipGetLastError();
         continue;

@@ -1525,10 +1525,10 @@ k_assign_small(const AssignProb* __restrict__ probs, const int32_t* __restrict__
 // workgroup's writes at agent scope, one relaxed increment, then polling until
 // every workgroup of the grid has arrived, and an agent-scope acquire.  The
 // counter only grows (target = waits so far x grid size), so no reset is
-// needed.  A wait that polls for more than kSyncSpins rounds (far beyond any
-// phase) raises the abort flag; every other waiting workgroup sees it and
-// leaves, so the kernel always ends, and every problem's status gets
-// kStatusSync.
+// needed.  A wait that polls more than max_spins times (kSyncSpins by
+// default, far beyond any phase) raises the abort flag; every other waiting
+// workgroup sees it and leaves, so the kernel always ends, and every
+// problem's status gets kStatusSync.
 // ---------------------------------------------------------------------------
 // Fixed-order sums of a pass's per-workgroup partials into its result record
 // (ss, sc: 256 entries of LDS each)
@@ -1562,9 +1562,7 @@ reduce_parts_prob(const ReduceProb& P, double* ss, unsigned long long* sc) {
   }
 }
 
-constexpr unsigned kSyncSpins = 1u << 25;  // s_sleep(2) polls: well over a second
-
-__device__ inline bool grid_wait(int* ctl, unsigned target, int* s_ok) {
+__device__ inline bool grid_wait(int* ctl, unsigned target, int* s_ok, unsigned max_spins) {
   __syncthreads();
   if (threadIdx.x == 0) {
     unsigned* arrivals = reinterpret_cast<unsigned*>(ctl);
@@ -1573,7 +1571,7 @@ __device__ inline bool grid_wait(int* ctl, unsigned target, int* s_ok) {
     int ok = 1;
     unsigned spins = 0;
     while (__hip_atomic_load(arrivals, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
-      if (__hip_atomic_load(ctl + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0 || ++spins > kSyncSpins) {
+      if (__hip_atomic_load(ctl + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0 || ++spins > max_spins) {
         ok = 0;
         break;
       }
@@ -1598,7 +1596,7 @@ __device__ inline int load_agent(const int* p) {
 template <class L, int XD, bool FALLBACK>
 __global__ void __launch_bounds__(kSmallThreads, 2)
 k_lloyd_rounds(const RoundProb* __restrict__ probs, int nprob, const int32_t* __restrict__ tpre,
-               const int32_t* __restrict__ cpre, const int32_t* __restrict__ fpre, int* ctl) {
+               const int32_t* __restrict__ cpre, const int32_t* __restrict__ fpre, int* ctl, unsigned max_spins) {
   extern __shared__ __attribute__((aligned(16))) char s_dyn[];
   __shared__ double s_sse[kOwnWaves];
   __shared__ double s_red[256];
@@ -1629,7 +1627,7 @@ k_lloyd_rounds(const RoundProb* __restrict__ probs, int nprob, const int32_t* __
       assign_small_tile<L, XD, FALLBACK>(probs[pi].a[b], t - tpre[pi], sm);
       __syncthreads();
     }
-    if (!grid_wait(ctl, ++waits * (unsigned)G, &s_ok)) break;
+    if (!grid_wait(ctl, ++waits * (unsigned)G, &s_ok, max_spins)) break;
     // chunk partials of the centre update
     for (int c = blockIdx.x; c < nchunk; c += G) {
       const int pi = find_problem(cpre, nprob, c);
@@ -1637,7 +1635,7 @@ k_lloyd_rounds(const RoundProb* __restrict__ probs, int nprob, const int32_t* __
       own_part_chunk<1, true>(probs[pi].u[b], c - cpre[pi], s_dyn, probs[pi].wstride, s_sse);
       __syncthreads();
     }
-    if (!grid_wait(ctl, ++waits * (unsigned)G, &s_ok)) break;
+    if (!grid_wait(ctl, ++waits * (unsigned)G, &s_ok, max_spins)) break;
     // per problem: counters of the pass (item 0), new centres of each
     // cluster group (items 1..nfin)
     for (int f = blockIdx.x; f < nfin; f += G) {
@@ -1648,7 +1646,7 @@ k_lloyd_rounds(const RoundProb* __restrict__ probs, int nprob, const int32_t* __
       else own_fin_group(probs[pi].u[b], item - 1, s_m, s_red);
       __syncthreads();
     }
-    if (!grid_wait(ctl, ++waits * (unsigned)G, &s_ok)) break;
+    if (!grid_wait(ctl, ++waits * (unsigned)G, &s_ok, max_spins)) break;
     // per problem: shift, SSE, stop test
     for (int pi = blockIdx.x; pi < nprob; pi += G) {
       if (s_done[pi]) continue;
@@ -1660,7 +1658,7 @@ k_lloyd_rounds(const RoundProb* __restrict__ probs, int nprob, const int32_t* __
       }
       __syncthreads();
     }
-    if (!grid_wait(ctl, ++waits * (unsigned)G, &s_ok)) break;
+    if (!grid_wait(ctl, ++waits * (unsigned)G, &s_ok, max_spins)) break;
   }
   // a wait gave up: mark every problem (the result records carry it)
   if (blockIdx.x == 0 && threadIdx.x == 0)
@@ -2041,7 +2039,7 @@ hipError_t launch_assign_small(int low, int xd, bool fallback, const AssignProb*
 template <class L, bool FALLBACK>
 static hipError_t launch_rounds_t(int xd, const RoundProb* dprobs, int nprob, const int32_t* tpre,
                                   const int32_t* cpre, const int32_t* fpre, int* ctl, int work_items,
-                                  int lds_bytes, hipStream_t st) {
+                                  int lds_bytes, unsigned max_spins, hipStream_t st) {
   const void* f = nullptr;
   switch (xd) {
     case 8: f = reinterpret_cast<const void*>(&k_lloyd_rounds<L, 8, FALLBACK>); break;
@@ -2058,14 +2056,16 @@ static hipError_t launch_rounds_t(int xd, const RoundProb* dprobs, int nprob, co
   if (e != hipSuccess) return e;
   if (per_cu < 1 || cus < 1) return hipErrorInvalidConfiguration;
   const int grid = std::max(1, std::min(per_cu * cus, work_items));
-  void* args[] = {(void*)&dprobs, (void*)&nprob, (void*)&tpre, (void*)&cpre, (void*)&fpre, (void*)&ctl};
+  void* args[] = {(void*)&dprobs, (void*)&nprob, (void*)&tpre, (void*)&cpre, (void*)&fpre, (void*)&ctl,
+                  (void*)&max_spins};
   return hipLaunchCooperativeKernel(f, dim3(grid), dim3(kSmallThreads), args, (unsigned)lds_bytes, st);
 }
 
 hipError_t launch_lloyd_rounds(int low, int xd, bool fallback, const RoundProb* dprobs, int nprob,
                                const int32_t* tpre, const int32_t* cpre, const int32_t* fpre, int* ctl,
-                               int work_items, int lds_bytes, hipStream_t st) {
-#define KM_ROUNDS(L, F) launch_rounds_t<L, F>(xd, dprobs, nprob, tpre, cpre, fpre, ctl, work_items, lds_bytes, st)
+                               int work_items, int lds_bytes, unsigned max_spins, hipStream_t st) {
+#define KM_ROUNDS(L, F) \
+  launch_rounds_t<L, F>(xd, dprobs, nprob, tpre, cpre, fpre, ctl, work_items, lds_bytes, max_spins, st)
   if (low == kLowFP16) return fallback ? KM_ROUNDS(LowF16, true) : KM_ROUNDS(LowF16, false);
   if (low == kLowBF16) return fallback ? KM_ROUNDS(LowBF16, true) : KM_ROUNDS(LowBF16, false);
 #undef KM_ROUNDS

@@ -235,9 +235,12 @@ constexpr int kRoundMaxProbs = 1024;  // problems of one persistent launch
 // chunks and finalize items (1 + nfin each).  Returns the runtime's error
 // when the grid cannot be co-resident; the caller then runs one launch per
 // phase.
+// max_spins: polls after which a grid-wide wait gives up (kSyncSpins unless
+// the KM_ROUND_SPIN_LIMIT environment variable sets it: tests of that path).
+constexpr unsigned kSyncSpins = 1u << 25;  // s_sleep(2) polls: well over a second
 hipError_t launch_lloyd_rounds(int low, int xd, bool fallback, const RoundProb* dprobs, int nprob,
                                const int32_t* tpre, const int32_t* cpre, const int32_t* fpre, int* ctl,
-                               int work_items, int lds_bytes, hipStream_t st);
+                               int work_items, int lds_bytes, unsigned max_spins, hipStream_t st);
 int small_lds_bytes(int xd, bool fallback);
 
 hipError_t launch_update_own_part(const UpdateProb* dprobs, const UpdateProb* hprobs, int nprob,

@@ -164,3 +164,20 @@ def test_batch_round_launch_equals_phase_launches(ctx, prec):
     for i, (x, y) in enumerate(zip(a, b)):
         print("problem", i, "iters", x[4]["iters"], flush=True)
         assert_same(x, y)
+
+
+def test_round_launch_gives_up_a_wait_and_reports_it(ctx, monkeypatch):
+    # a host-set cap of one poll per grid-wide wait forces the give-up path:
+    # the waiting workgroup raises the abort flag, every workgroup leaves, the
+    # launch ends and the call reports a device error; the context stays usable
+    X, _, _ = W.blobs(20_000, 32, 16, seed=1)
+    C0 = W.init_centroids(X, 16, 2)
+    Xd = dev(X)
+    monkeypatch.setenv("KM_ROUND_SPIN_LIMIT", "1")
+    for tol in (0.0, 1e-6):
+        with pytest.raises(km.KMeansError) as err:
+            km.kmeans_lloyd(ctx, Xd, dev(C0), 20, tol=tol, prec=FP16, stats=True, round_launch=True)
+        assert err.value.code == km.KM_ERR_DEVICE, err.value
+    monkeypatch.delenv("KM_ROUND_SPIN_LIMIT")
+    a, b = both(ctx, X, C0, 5, FP16)
+    assert_same(a, b)
