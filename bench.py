@@ -476,7 +476,7 @@ def main():
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": MFMA_FP16_PEAK_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / MFMA_FP16_PEAK_TFLOPS,
                      "traffic": measured_traffic(),
-                     "kernel": "k_assign_pipe<LowF16,128,2,true>",
+                     "kernel": "k_assign_pipe<LowF16,128,2,true,false>",
                      "kernel_avg_ms": kern_avg_ms,
                      "algorithmic_flops_per_launch": flops},
     }
