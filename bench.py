@@ -337,7 +337,9 @@ def batch_bench(km, ctx, torch, W, np, count=256, iters=30):
     tp, lp = batched(round_launch=True)
     same_p = all(bool(torch.equal(a, b)) for a, b in zip(lp, ls))
     passes = iters + 1
-    # algorithmic bytes of an assignment pass: read X once, write the labels
+    # algorithmic bytes of an assignment pass: read X once, write the labels;
+    # the rate below divides every pass's bytes by the whole batched solve
+    # (centre updates included), not by the assignment kernels alone
     alg_bytes = float(total_n) * (4 * d + 4) * passes
     out = {"problems": count, "points": total_n, "d": d, "rounds": iters,
            "batched_s": tb, "one_by_one_s": ts, "speedup": ts / tb,
