@@ -407,15 +407,15 @@ int32_t kmeans_timing_read(km_context *ctx, float *ms_out, int32_t max,
 
 /* ---- tuning cache ---------------------------------------------------------
  * kmeans_solve_batch times the first rounds of its small-problem launches
- * with 2, 4, 8 and 16 groups of 32 points per wave and keeps the fastest; the
- * choice is remembered per shape bucket (low format, correction precision,
- * threshold on/off, largest kernel row capacity, largest padded k, total
- * points rounded down to a power of two) in the context, and a later batch
- * of the same bucket uses it without timing.  Results never depend on the
- * choice.
+ * with 2, 4, 8, 16 and 32 groups of 32 points per wave and keeps the
+ * fastest; the choice is remembered per shape bucket (low format,
+ * correction precision, threshold on/off, largest kernel row capacity,
+ * largest padded k, total points rounded down to a power of two) in the
+ * context, and a later batch of the same bucket uses it without timing.
+ * Results never depend on the choice.
  * kmeans_tune_cache: a file that makes the choices persistent (read now if it
  *   exists, rewritten after every new choice; one text line per bucket: key,
- *   groups per wave, the four times in ms).  NULL or "" keeps them in
+ *   groups per wave, the five times in ms).  NULL or "" keeps them in
  *   memory only.  Returns KM_OK or KM_ERR_ARG.
  * kmeans_tune_dump: the cache as that text, NUL-terminated and cut to cap-1
  *   bytes; returns the full length (call with cap 0 to size the buffer). */

@@ -1549,7 +1549,7 @@ extern "C" int32_t kmeans_solve_batch(km_context* ctx, km_problem* probs, int32_
   bool need_tol = false;
   for (int i = 0; i < count; ++i) need_tol |= probs[i].tol > 0.0;
   // Sweep-length tuner of the small-problem launches: the first rounds run
-  // with 2, 4, 8 and 16 groups per wave (never fewer than a problem's own,
+  // with 2, 4, 8, 16 and 32 groups per wave (never fewer than a problem's own,
   // whose partials bound the workspace; timed with events around the
   // assignment launches) and the fastest is kept for the rest.  These are
   // real rounds: labels and counts do not depend on the partition and the
@@ -1557,8 +1557,8 @@ extern "C" int32_t kmeans_solve_batch(km_context* ctx, km_problem* probs, int32_
   // chosen (the final pass uses each problem's own partition).
   // A choice made before for the same shape bucket (the context's tuning
   // cache, persisted when the caller gave it a file) is used without tuning.
-  static constexpr int kTuneN = 4;
-  static const int kTuneGpw[kTuneN] = {2, 4, 8, 16};
+  static constexpr int kTuneN = 5;
+  static const int kTuneGpw[kTuneN] = {2, 4, 8, 16, 32};
   bool tune = false;
   std::string tune_key;
   int cached_gpw = 0;

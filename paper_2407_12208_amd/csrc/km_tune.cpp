@@ -52,7 +52,7 @@ int32_t TuneCache::set_path(const char* p) {
     std::istringstream ls(line);
     std::string k;
     Entry e{};
-    if (!(ls >> k >> e.gpw) || (e.gpw != 1 && e.gpw != 2 && e.gpw != 4 && e.gpw != 8 && e.gpw != 16))
+    if (!(ls >> k >> e.gpw) || (e.gpw != 1 && e.gpw != 2 && e.gpw != 4 && e.gpw != 8 && e.gpw != 16 && e.gpw != 32))
       continue;  // malformed lines are ignored
     float t;
     while (ls >> t) e.ms.push_back(t);

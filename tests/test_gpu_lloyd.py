@@ -314,7 +314,7 @@ def test_batch_equals_alone_when_the_launch_sweeps_longer(ctx):
 
 def test_batch_tuner_choice_is_cached_persisted_and_harmless(ctx, tmp_path):
     # eight segmentation-shaped problems (2.6 M points in one small-problem
-    # launch): the first batched solve times 2, 4, 8 and 16 groups per wave and
+    # launch): the first batched solve times 2, 4, 8, 16 and 32 groups per wave and
     # records the fastest for the launch's shape bucket; a second solve of
     # the same bucket, in a new context reading the persisted file, uses the
     # choice without timing; the results are bitwise the same either way
@@ -334,7 +334,7 @@ def test_batch_tuner_choice_is_cached_persisted_and_harmless(ctx, tmp_path):
     lines = [l for l in text.splitlines() if l.strip()]
     assert len(lines) == 1 and lines[0].startswith("small:low=0:high=0:fb=1:xd=8:")
     gpw = int(lines[0].split()[1])
-    assert gpw in (2, 4, 8, 16) and len(lines[0].split()) == 6
+    assert gpw in (2, 4, 8, 16, 32) and len(lines[0].split()) == 7
     with open(path) as f:
         assert f.read() == text
     c1.close()
